@@ -1,0 +1,158 @@
+"""Throughput of the FHT + bend-limited DP polyline detector on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--config C3]
+
+One step is one whole detection (band FHT of all k bands, the DP over every
+band boundary, the argmax and the backtrace) of one seeded synthetic image
+that is already resident in HBM.  The default workload is the 4096x4096
+uint16 image with k = 32 bands of 128 rows and a bend bound of 8 shifts.
+Prints one JSON line.  The CPU oracle is timed on a bounded sample of the
+same workload beside it.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def byte_model(h, w, k, bpp):
+    """Algorithmic HBM bytes of one detection with materialised band tables."""
+    n = h // k
+    D, W = 2 * n - 1, w + n
+    image = h * w * bpp
+    tables = 4 * k * D * W
+    backptr = (k - 1) * D * w * (1 if D <= 256 else 2)
+    return {"image": image, "tables_write": tables, "tables_read": tables, "backptr": backptr,
+            "total": image + 2 * tables + backptr, "fht_kernel": image + tables}
+
+
+def time_events(fn, reps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / reps  # ms per call
+
+
+def cpu_baseline(img, k, bend, seconds):
+    import oracle
+    h, w = img.shape
+    runs = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.detect_polyline(img, k, bend=bend)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": round(h * w * runs / el / 1e6, 3), "unit": "Mpix/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{runs} full detection(s) of the {h}x{w} image, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="C3", choices=["C1", "C2", "C3"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
+              "(the detector runs one image per GPU; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1912_01884_amd import fhtp
+
+    s = synth.make_config(args.config)
+    h, w, k, B = s.h, s.w, s.k, s.bend
+    bpp = s.image.dtype.itemsize
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    img = torch.from_numpy(s.image).to(dev)
+    dt = fhtp.FHTP_U8 if bpp == 1 else fhtp.FHTP_U16
+    bend = fhtp.make_bend(B)
+    ws = torch.empty(fhtp.detect_workspace_bytes(dt, h, w, k, bend), dtype=torch.uint8, device=dev)
+    score = torch.empty(1, dtype=torch.int32, device=dev)
+    xs = torch.empty(k + 1, dtype=torch.int32, device=dev)
+
+    def step():
+        fhtp.detect_polyline(img, k, bend=B, ws=ws, score=score, xs=xs, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_events = time_events(step, args.steps, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = max(ms_events, 1e-9)
+
+    # Phase timings on the same stream: the band FHT (one kernel) and the DP.
+    tables = torch.empty(fhtp.table_shape(h, w, k), dtype=torch.int32, device=dev)
+    fws_n = fhtp.fht_workspace_bytes(dt, h, w, k)
+    fws = torch.empty(max(fws_n, 1), dtype=torch.uint8, device=dev)
+    dws = torch.empty(fhtp.dp_workspace_bytes(h, w, k, bend), dtype=torch.uint8, device=dev)
+    ms_fht = time_events(lambda: fhtp.fht_bands(img, k, tables=tables, ws=fws if fws_n else None,
+                                                stream=stream), args.steps, stream)
+    ms_dp = time_events(lambda: fhtp.polyline_dp(tables, h, w, k, bend=B, ws=dws, score=score,
+                                                 xs=xs, stream=stream), args.steps, stream)
+
+    model = byte_model(h, w, k, bpp)
+    fht_gbps = model["fht_kernel"] / (ms_fht * 1e-3) / 1e9
+    line = {
+        "metric": "FHT+DP Mpix/s @4096x4096,k=32 (HBM GB/s beside it)",
+        "value": round(h * w / (ms_per_step * 1e-3) / 1e6, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "wall_ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {h}x{w} {s.image.dtype.name} image, k={k} "
+                               f"bands of {h // k} rows, bend bound {B} shifts, one image per step",
+                   "h": h, "w": w, "k": k, "bend": B, "pixel": s.image.dtype.name},
+        "images_per_s": round(1e3 / ms_per_step, 2),
+        "hbm_gbps_model": round(model["total"] / (ms_per_step * 1e-3) / 1e9, 1),
+        "model_bytes": model,
+        "phase_ms": {"fht_bands": round(ms_fht, 4), "polyline_dp": round(ms_dp, 4)},
+        "roofline": {"bound": "hbm", "kernel": "fht_reg_kernel",
+                     "achieved": round(fht_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(fht_gbps / HBM_PEAK_GBPS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(s.image, k, B, args.cpu_seconds)
+    res = (int(score.cpu()[0]), xs.cpu().numpy().tolist())
+    line["result"] = {"score": res[0], "x0": res[1][0], "xk": res[1][-1]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

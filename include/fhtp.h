@@ -1,0 +1,150 @@
+/*
+ * fhtp.h -- C ABI of libfhtp.so: end-to-end curves of limited curvature on MI355X.
+ *
+ * The library finds the k-link "mostly vertical uniform polyline" (paper:
+ * "A Method of Detecting End-To-End Curves of Limited Curvature", Section 2,
+ * definitions 1-5 and the main problem statement) whose summed pixel values
+ * are largest, subject to a bound on the bend between adjacent links.  It
+ * follows the paper's method: a Fast Hough Transform of every horizontal band
+ * (Section 2.1), then a bottom-up dynamic programme over band boundaries with
+ * a range maximum over admissible successors (Sections 2.2-2.3, eqs. (3)-(7)),
+ * then the global choice and backtrace (eq. (5) and the main-problem steps 2-3).
+ *
+ * Geometry and notation (the paper leaves the discrete details open; these are
+ * the readings the library implements):
+ *   - the image is h rows by w columns, row-major, no padding (stride w);
+ *   - k bands of n = h/k rows each; n must be a power of two, n <= 1024;
+ *   - each band is extended to the right by n zero columns (Section 2.1), so
+ *     band tables are W = w + n columns wide and cyclic over W;
+ *   - a link over band i starts at column x on the band's first row and is
+ *     displaced by d in [-(n-1), n-1] columns on its last row, following the
+ *     dyadic digital line of the FHT (upper half with shift floor(s/2), lower
+ *     half offset by ceil(s/2), mirrored for d < 0);
+ *   - the paper's Hough coordinate of eq. (1) is shift = n - d; this ABI
+ *     indexes table rows by r = d + n - 1 instead;
+ *   - a polyline is (x_0; d_0 .. d_{k-1}) with x_{i+1} = x_i + d_i, every
+ *     vertex x_0 .. x_k inside [0, w-1]; x_k is the column on the last row;
+ *   - its score is the sum of one pixel per image row along it (Section 2.1);
+ *   - bend mode 0: |d_{i+1} - d_i| <= shift_bound;
+ *     bend mode 1: |atan(d_{i+1}/n) - atan(d_i/n)| <= gamma_rad, the angle
+ *     form of eqs. (6)-(7), decided exactly as
+ *     n*|d' - d| <= tan(gamma) * (n*n + d*d') in IEEE double (gamma >= pi/2
+ *     admits every pair);
+ *   - among polylines with the best score the lexicographically smallest
+ *     (x_0, d_0, d_1, ..., d_{k-1}) is returned.
+ *   All arithmetic is integer and exact; results are bit-identical to the
+ *   CPU definition.
+ *
+ * Conventions for every entry point:
+ *   - return FHTP_OK (0) or a negative FHTP_ERR_* code;
+ *   - all arguments are validated on the host before anything is enqueued;
+ *     on error nothing is enqueued and no output is touched;
+ *   - compute calls are asynchronous on `stream` (a hipStream_t passed as
+ *     void*, NULL = the default stream); outputs are valid once the stream
+ *     has been synchronised;
+ *   - every data pointer of a compute call is DEVICE memory owned by the
+ *     caller; the library never allocates, frees or synchronises it;
+ *   - `ws` is caller-owned device scratch of at least the size reported by
+ *     the matching *_workspace_bytes query, aligned to 256 bytes; its
+ *     contents on entry do not matter; two calls that share a workspace must
+ *     be ordered on one stream;
+ *   - size queries are pure host functions and never touch the GPU.
+ */
+#ifndef FHTP_H
+#define FHTP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Pixel types of the input image. */
+typedef enum { FHTP_U8 = 0, FHTP_U16 = 1 } fhtp_dtype;
+
+/* Bend restriction between adjacent links (Section 2.3).
+ * mode 0: |d_{i+1} - d_i| <= shift_bound (shift_bound >= 0; gamma_rad ignored).
+ * mode 1: bending angle <= gamma_rad (finite, >= 0; shift_bound ignored). */
+typedef struct {
+    int32_t mode;
+    int32_t shift_bound;
+    double gamma_rad;
+} fhtp_bend;
+
+#define FHTP_OK 0
+#define FHTP_ERR_NULL (-1)        /* a required pointer is NULL */
+#define FHTP_ERR_DIMS (-2)        /* h,w,k <= 0; k does not divide h; n not a power of two;
+                                     n > 1024; w > 2^20 */
+#define FHTP_ERR_BEND (-3)        /* bad mode, negative bound, gamma not finite or < 0 */
+#define FHTP_ERR_OVERFLOW (-4)    /* h * maxval(dtype) >= 2^31: a score might not fit int32 */
+#define FHTP_ERR_WORKSPACE (-5)   /* workspace too small or not 256-byte aligned */
+#define FHTP_ERR_HIP (-6)         /* HIP launch or runtime failure; see fhtp_last_error_detail */
+#define FHTP_ERR_UNSUPPORTED (-7) /* valid request this build does not implement */
+#define FHTP_ERR_DTYPE (-8)       /* dtype is not FHTP_U8 or FHTP_U16 */
+#define FHTP_ERR_POINT (-9)       /* through-point query outside the image or band grid */
+
+/* Human-readable name of an error code (static storage). */
+const char* fhtp_strerror(int code);
+
+/* Detail of the last FHTP_ERR_HIP on the calling thread (thread-local storage). */
+const char* fhtp_last_error_detail(void);
+
+/* Library version string (static storage). */
+const char* fhtp_version(void);
+
+/* Shape of the band tables: bands = k, shifts = 2n-1, width = w+n.
+ * Validates h, w, k as above (the pixel type is not involved). */
+int fhtp_table_shape(int h, int w, int k, int64_t* bands, int64_t* shifts, int64_t* width);
+
+/* ---------------------------------------------------------------------------
+ * Band FHT (Section 2.1, "Subproblem 1"): the Hough image for mostly vertical
+ * lines of every zero-extended band.
+ *
+ *   tables[i][d + n - 1][x] = sum over band rows y of
+ *       pixel(i*n + y, (x + sign(d) * D_{|d|}(y)) mod W),  pixel = 0 beyond column w-1,
+ *   for i in [0,k), d in [-(n-1), n-1], x in [0, W).
+ *
+ * img:    device, [h][w] of uint8 or uint16 (per `dtype`), read only.
+ * tables: device, [k][2n-1][W] int32, written in full.
+ * ws:     device scratch, fhtp_fht_workspace_bytes(...) bytes (0 for n <= 128).
+ * Cost: O(W * h * log n) additions (Section 2.1, asymptotic complexity).
+ * ------------------------------------------------------------------------- */
+int fhtp_fht_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, size_t* bytes);
+int fhtp_fht_bands(const void* img, fhtp_dtype dtype, int h, int w, int k, int32_t* tables,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Bend-limited polyline DP over given band tables (Sections 2.2-2.3, eqs.
+ * (3)-(7); main problem steps 2-3; backtrace by eq. (5)).
+ *
+ * tables: device, [k][2n-1][W] int32 in the layout written by fhtp_fht_bands
+ *         (only columns x < w are read); every entry must be >= 0 and the sum
+ *         along any polyline must be < 2^31 (true for tables of an image that
+ *         passes validation).
+ * score:  device, 1 int32: the best polyline score.
+ * xs:     device, k+1 int32: x_0 .. x_k (x_i on row i*n for i < k, x_k on row h-1).
+ * ws:     device scratch, fhtp_dp_workspace_bytes(...) bytes.
+ * ------------------------------------------------------------------------- */
+int fhtp_dp_workspace_bytes(int h, int w, int k, fhtp_bend bend, size_t* bytes);
+int fhtp_polyline_dp(const int32_t* tables, int h, int w, int k, fhtp_bend bend, void* ws,
+                     size_t ws_bytes, int32_t* score, int32_t* xs, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * The whole detector: band FHT, then the DP, then the backtrace (the paper's
+ * main problem without its Gaussian pre-filter; the input is taken as the
+ * already filtered or gradient image).
+ *
+ * img, dtype, h, w, k as fhtp_fht_bands; bend, score, xs as fhtp_polyline_dp.
+ * ws: device scratch, fhtp_detect_workspace_bytes(...) bytes (holds the tables).
+ * ------------------------------------------------------------------------- */
+int fhtp_detect_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
+                                size_t* bytes);
+int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
+                         void* ws, size_t ws_bytes, int32_t* score, int32_t* xs, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FHTP_H */

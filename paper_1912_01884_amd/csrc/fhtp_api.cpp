@@ -1,0 +1,260 @@
+// Host side of the C ABI declared in include/fhtp.h: validation, workspace
+// layout, window planning and kernel dispatch.  Every check runs on the host
+// before anything is enqueued, so a rejected call leaves the stream and the
+// outputs untouched.
+#include "fhtp.h"
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "fhtp_internal.h"
+
+namespace {
+
+thread_local std::string g_detail;
+
+constexpr int kMaxN = 1024;
+constexpr int kMaxW = 1 << 20;
+constexpr int kMaxFixedB = 16;
+constexpr size_t kAlign = 256;
+// pi/2 rounded to double: at or above it every bend is admissible.
+constexpr double kHalfPi = 1.57079632679489661923;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int shape(int h, int w, int k, fhtp::Geometry* g) {
+    if (h <= 0 || w <= 0 || k <= 0) return FHTP_ERR_DIMS;
+    if (h % k != 0) return FHTP_ERR_DIMS;
+    const int n = h / k;
+    if (!is_pow2(n) || n > kMaxN) return FHTP_ERR_DIMS;
+    if (w > kMaxW) return FHTP_ERR_DIMS;
+    int p = 0;
+    while ((1 << p) < n) ++p;
+    g->h = h;
+    g->w = w;
+    g->k = k;
+    g->n = n;
+    g->p = p;
+    g->W = w + n;
+    g->D = 2 * n - 1;
+    g->pitch = (w + 63) / 64 * 64;
+    return FHTP_OK;
+}
+
+// A polyline takes one pixel per row, so its score is at most h * maxval.
+int pixels(fhtp_dtype dtype, int h) {
+    if (dtype != FHTP_U8 && dtype != FHTP_U16) return FHTP_ERR_DTYPE;
+    const long long maxval = dtype == FHTP_U8 ? 255 : 65535;
+    if ((long long)h * maxval >= (1LL << 31)) return FHTP_ERR_OVERFLOW;
+    return FHTP_OK;
+}
+
+int plan(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
+    pl->a16 = g.D > 256;
+    pl->bound = 0;
+    pl->tan_gamma = 0.0;
+    if (b.mode == 0) {
+        if (b.shift_bound < 0) return FHTP_ERR_BEND;
+        pl->bound = b.shift_bound;
+        if ((long long)b.shift_bound >= 2LL * g.n - 2)
+            pl->kind = fhtp::WindowKind::Full;
+        else if (b.shift_bound <= kMaxFixedB)
+            pl->kind = fhtp::WindowKind::Fixed;
+        else
+            pl->kind = fhtp::WindowKind::Generic;
+        return FHTP_OK;
+    }
+    if (b.mode == 1) {
+        if (!std::isfinite(b.gamma_rad) || b.gamma_rad < 0.0) return FHTP_ERR_BEND;
+        if (b.gamma_rad >= kHalfPi) {
+            pl->kind = fhtp::WindowKind::Full;
+        } else {
+            pl->kind = fhtp::WindowKind::Angle;
+            pl->tan_gamma = std::tan(b.gamma_rad);
+        }
+        return FHTP_OK;
+    }
+    return FHTP_ERR_BEND;
+}
+
+struct DpLayout {
+    size_t v0, v1, a, key, win, end;
+};
+
+DpLayout dp_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, size_t base) {
+    DpLayout L;
+    L.v0 = base;
+    L.v1 = align_up(L.v0 + fhtp::dp_plane_bytes(g));
+    L.a = align_up(L.v1 + fhtp::dp_plane_bytes(g));
+    L.key = align_up(L.a + fhtp::dp_backptr_bytes(g, pl.a16));
+    L.win = align_up(L.key + sizeof(unsigned long long));
+    L.end = align_up(L.win + 2 * (size_t)g.D * sizeof(int32_t));
+    return L;
+}
+
+struct DetectLayout {
+    size_t tables, scratch;
+    DpLayout dp;
+};
+
+DetectLayout detect_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl) {
+    DetectLayout L;
+    L.tables = 0;
+    L.scratch = align_up((size_t)g.k * g.D * (size_t)g.W * sizeof(int32_t));
+    L.dp = dp_layout(g, pl, align_up(L.scratch + fhtp::fht_scratch_bytes(g)));
+    return L;
+}
+
+fhtp::DpBuffers dp_buffers(char* ws, const DpLayout& L) {
+    fhtp::DpBuffers b;
+    b.v[0] = reinterpret_cast<int32_t*>(ws + L.v0);
+    b.v[1] = reinterpret_cast<int32_t*>(ws + L.v1);
+    b.a = ws + L.a;
+    b.key = reinterpret_cast<unsigned long long*>(ws + L.key);
+    b.win = reinterpret_cast<int32_t*>(ws + L.win);
+    return b;
+}
+
+int check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return FHTP_OK;
+    if (!ws) return FHTP_ERR_NULL;
+    if (ws_bytes < need) return FHTP_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return FHTP_ERR_WORKSPACE;
+    return FHTP_OK;
+}
+
+int hip_status(hipError_t e, const char* where) {
+    if (e == hipSuccess) return FHTP_OK;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+    g_detail = buf;
+    return FHTP_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fhtp_strerror(int code) {
+    switch (code) {
+        case FHTP_OK: return "ok";
+        case FHTP_ERR_NULL: return "null pointer";
+        case FHTP_ERR_DIMS: return "invalid dimensions (need h,w,k > 0, k | h, n = h/k a power of two <= 1024, w <= 2^20)";
+        case FHTP_ERR_BEND: return "invalid bend restriction";
+        case FHTP_ERR_OVERFLOW: return "scores could overflow int32 (h * maxval >= 2^31)";
+        case FHTP_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
+        case FHTP_ERR_HIP: return "HIP runtime error";
+        case FHTP_ERR_UNSUPPORTED: return "unsupported request";
+        case FHTP_ERR_DTYPE: return "invalid pixel type";
+        case FHTP_ERR_POINT: return "point outside the image or band grid";
+        default: return "unknown error";
+    }
+}
+
+const char* fhtp_last_error_detail(void) { return g_detail.c_str(); }
+
+const char* fhtp_version(void) { return "fhtp 0.1.0 gfx950"; }
+
+int fhtp_table_shape(int h, int w, int k, int64_t* bands, int64_t* shifts, int64_t* width) {
+    if (!bands || !shifts || !width) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    int rc = shape(h, w, k, &g);
+    if (rc != FHTP_OK) return rc;
+    *bands = g.k;
+    *shifts = g.D;
+    *width = g.W;
+    return FHTP_OK;
+}
+
+int fhtp_fht_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, size_t* bytes) {
+    if (!bytes) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    int rc = shape(h, w, k, &g);
+    if (rc == FHTP_OK) rc = pixels(dtype, h);
+    if (rc != FHTP_OK) return rc;
+    *bytes = fhtp::fht_scratch_bytes(g);
+    return FHTP_OK;
+}
+
+int fhtp_fht_bands(const void* img, fhtp_dtype dtype, int h, int w, int k, int32_t* tables,
+                   void* ws, size_t ws_bytes, void* stream) {
+    if (!img || !tables) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    int rc = shape(h, w, k, &g);
+    if (rc == FHTP_OK) rc = pixels(dtype, h);
+    if (rc == FHTP_OK) rc = check_ws(ws, ws_bytes, fhtp::fht_scratch_bytes(g));
+    if (rc != FHTP_OK) return rc;
+    (void)hipGetLastError();
+    return hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, ws,
+                                       static_cast<hipStream_t>(stream)),
+                      "fht_bands");
+}
+
+int fhtp_dp_workspace_bytes(int h, int w, int k, fhtp_bend bend, size_t* bytes) {
+    if (!bytes) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    fhtp::DpPlan pl;
+    int rc = shape(h, w, k, &g);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc != FHTP_OK) return rc;
+    *bytes = dp_layout(g, pl, 0).end;
+    return FHTP_OK;
+}
+
+int fhtp_polyline_dp(const int32_t* tables, int h, int w, int k, fhtp_bend bend, void* ws,
+                     size_t ws_bytes, int32_t* score, int32_t* xs, void* stream) {
+    if (!tables || !score || !xs) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    fhtp::DpPlan pl;
+    int rc = shape(h, w, k, &g);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc != FHTP_OK) return rc;
+    const DpLayout L = dp_layout(g, pl, 0);
+    rc = check_ws(ws, ws_bytes, L.end);
+    if (rc != FHTP_OK) return rc;
+    (void)hipGetLastError();
+    return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(static_cast<char*>(ws), L), score,
+                                      xs, static_cast<hipStream_t>(stream)),
+                      "polyline_dp");
+}
+
+int fhtp_detect_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
+                                size_t* bytes) {
+    if (!bytes) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    fhtp::DpPlan pl;
+    int rc = shape(h, w, k, &g);
+    if (rc == FHTP_OK) rc = pixels(dtype, h);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc != FHTP_OK) return rc;
+    *bytes = detect_layout(g, pl).dp.end;
+    return FHTP_OK;
+}
+
+int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
+                         void* ws, size_t ws_bytes, int32_t* score, int32_t* xs, void* stream) {
+    if (!img || !score || !xs) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    fhtp::DpPlan pl;
+    int rc = shape(h, w, k, &g);
+    if (rc == FHTP_OK) rc = pixels(dtype, h);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc != FHTP_OK) return rc;
+    const DetectLayout L = detect_layout(g, pl);
+    rc = check_ws(ws, ws_bytes, L.dp.end);
+    if (rc != FHTP_OK) return rc;
+    char* base = static_cast<char*>(ws);
+    int32_t* tables = reinterpret_cast<int32_t*>(base + L.tables);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s),
+                    "detect_polyline/fht");
+    if (rc != FHTP_OK) return rc;
+    return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(base, L.dp), score, xs, s),
+                      "detect_polyline/dp");
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Internal declarations shared by the host API and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fhtp {
+
+// Problem geometry derived from (h, w, k) after validation.
+struct Geometry {
+    int h, w, k;
+    int n;   // band height h/k, a power of two
+    int p;   // log2(n)
+    int W;   // table width w + n (zero extension of Section 2.1)
+    int D;   // shifts per band 2n - 1
+    int pitch;  // row pitch (elements) of the DP planes: w rounded up to 64
+};
+
+// Largest band height the register FHT kernel handles in one pass.
+constexpr int kRegMaxP = 7;
+
+// ---- band FHT -------------------------------------------------------------
+// Scratch needed by launch_fht (bytes, 0 when n <= 2^kRegMaxP).
+size_t fht_scratch_bytes(const Geometry& g);
+// Writes tables [k][D][W] int32.  dtype 0 = uint8, 1 = uint16.
+hipError_t launch_fht(const void* img, int dtype, const Geometry& g, int32_t* tables,
+                      void* scratch, hipStream_t stream);
+
+// ---- DP ---------------------------------------------------------------------
+// How the DP step takes its range maximum.
+enum class WindowKind { Fixed, Generic, Full, Angle };
+
+struct DpPlan {
+    WindowKind kind;
+    int bound;          // mode 0 shift bound
+    double tan_gamma;   // mode 1
+    bool a16;           // back-pointers stored as uint16 (D > 256) instead of uint8
+};
+
+struct DpBuffers {
+    int32_t* v[2];            // ping-pong value planes [D][pitch]
+    void* a;                  // back-pointer planes [k-1][D][pitch]
+    unsigned long long* key;  // packed argmax key
+    int32_t* win;             // angle windows lo[D], hi[D]
+};
+
+size_t dp_plane_bytes(const Geometry& g);
+size_t dp_backptr_bytes(const Geometry& g, bool a16);
+hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
+                     const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream);
+
+}  // namespace fhtp

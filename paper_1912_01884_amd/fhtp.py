@@ -1,0 +1,224 @@
+"""Thin ctypes binding of libfhtp.so, with torch tensors as device buffers.
+
+Argument marshalling only: every step of the detector runs in the HIP kernels
+behind the C ABI (include/fhtp.h).  torch provides device memory and the
+stream; the library itself never allocates.  If libfhtp.so has not been built
+this module raises on first use -- there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfhtp.so")
+
+FHTP_U8 = 0
+FHTP_U16 = 1
+
+OK = 0
+ERR_NULL = -1
+ERR_DIMS = -2
+ERR_BEND = -3
+ERR_OVERFLOW = -4
+ERR_WORKSPACE = -5
+ERR_HIP = -6
+ERR_UNSUPPORTED = -7
+ERR_DTYPE = -8
+ERR_POINT = -9
+
+EXPORTED = (
+    "fhtp_strerror", "fhtp_last_error_detail", "fhtp_version", "fhtp_table_shape",
+    "fhtp_fht_workspace_bytes", "fhtp_fht_bands", "fhtp_dp_workspace_bytes", "fhtp_polyline_dp",
+    "fhtp_detect_workspace_bytes", "fhtp_detect_polyline",
+)
+
+
+class FhtpError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        msg = f"{what} failed: {strerror(code)} ({code})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+        self.code = code
+
+
+class Bend(C.Structure):
+    """fhtp_bend: mode 0 = |d_{i+1}-d_i| <= shift_bound, mode 1 = bend angle <= gamma_rad."""
+
+    _fields_ = [("mode", C.c_int32), ("shift_bound", C.c_int32), ("gamma_rad", C.c_double)]
+
+
+def make_bend(bend: Optional[int] = None, gamma: Optional[float] = None) -> Bend:
+    if gamma is not None:
+        return Bend(1, 0, float(gamma))
+    if bend is None:
+        raise ValueError("give either a shift bound (bend=) or an angle bound (gamma=)")
+    return Bend(0, int(bend), 0.0)
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libfhtp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    vp, sz, i32, i64p = C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_int64)
+    szp = C.POINTER(C.c_size_t)
+    L.fhtp_strerror.argtypes = [i32]
+    L.fhtp_strerror.restype = C.c_char_p
+    L.fhtp_last_error_detail.restype = C.c_char_p
+    L.fhtp_version.restype = C.c_char_p
+    L.fhtp_table_shape.argtypes = [i32, i32, i32, i64p, i64p, i64p]
+    L.fhtp_fht_workspace_bytes.argtypes = [i32, i32, i32, i32, szp]
+    L.fhtp_fht_bands.argtypes = [vp, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.fhtp_dp_workspace_bytes.argtypes = [i32, i32, i32, Bend, szp]
+    L.fhtp_polyline_dp.argtypes = [vp, i32, i32, i32, Bend, vp, sz, vp, vp, vp]
+    L.fhtp_detect_workspace_bytes.argtypes = [i32, i32, i32, i32, Bend, szp]
+    L.fhtp_detect_polyline.argtypes = [vp, i32, i32, i32, i32, Bend, vp, sz, vp, vp, vp]
+    for name in EXPORTED:
+        if name not in ("fhtp_strerror", "fhtp_last_error_detail", "fhtp_version"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().fhtp_strerror(int(code)).decode()
+
+
+def version() -> str:
+    return lib().fhtp_version().decode()
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        detail = lib().fhtp_last_error_detail().decode() if rc == ERR_HIP else ""
+        raise FhtpError(rc, what, detail)
+
+
+# ---- pure host queries ------------------------------------------------------
+
+def table_shape(h: int, w: int, k: int) -> Tuple[int, int, int]:
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().fhtp_table_shape(h, w, k, C.byref(a), C.byref(b), C.byref(c)), "table_shape")
+    return a.value, b.value, c.value
+
+
+def fht_workspace_bytes(dtype: int, h: int, w: int, k: int) -> int:
+    out = C.c_size_t()
+    _check(lib().fhtp_fht_workspace_bytes(dtype, h, w, k, C.byref(out)), "fht_workspace_bytes")
+    return out.value
+
+
+def dp_workspace_bytes(h: int, w: int, k: int, bend: Bend) -> int:
+    out = C.c_size_t()
+    _check(lib().fhtp_dp_workspace_bytes(h, w, k, bend, C.byref(out)), "dp_workspace_bytes")
+    return out.value
+
+
+def detect_workspace_bytes(dtype: int, h: int, w: int, k: int, bend: Bend) -> int:
+    out = C.c_size_t()
+    _check(lib().fhtp_detect_workspace_bytes(dtype, h, w, k, bend, C.byref(out)),
+           "detect_workspace_bytes")
+    return out.value
+
+
+# ---- torch marshalling ------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.uint8:
+        return FHTP_U8
+    if t.dtype == torch.uint16:
+        return FHTP_U16
+    raise TypeError(f"image must be uint8 or uint16, got {t.dtype}")
+
+
+def _stream_ptr(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _require_device(t, name: str):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+
+
+def _ws(nbytes: int, device, ws):
+    torch = _torch()
+    if nbytes == 0:
+        return None, 0
+    if ws is not None:
+        return ws, ws.numel() * ws.element_size()
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def fht_bands(img, k: int, tables=None, ws=None, stream=None):
+    """Band tables [k][2n-1][w+n] int32 of a device image [h][w] (uint8 or uint16)."""
+    torch = _torch()
+    _require_device(img, "img")
+    h, w = img.shape
+    dt = _dtype_code(img)
+    kk, D, W = table_shape(h, w, k)
+    if tables is None:
+        tables = torch.empty((kk, D, W), dtype=torch.int32, device=img.device)
+    ws_t, ws_n = _ws(fht_workspace_bytes(dt, h, w, k), img.device, ws)
+    rc = lib().fhtp_fht_bands(img.data_ptr(), dt, h, w, k, tables.data_ptr(), _ptr(ws_t), ws_n,
+                              _stream_ptr(stream))
+    _check(rc, "fht_bands")
+    return tables
+
+
+def polyline_dp(tables, h: int, w: int, k: int, bend: Optional[int] = None,
+                gamma: Optional[float] = None, ws=None, score=None, xs=None, stream=None):
+    """Best score (1 int32) and vertices x_0..x_k (k+1 int32) as device tensors."""
+    torch = _torch()
+    _require_device(tables, "tables")
+    b = make_bend(bend, gamma)
+    if score is None:
+        score = torch.empty(1, dtype=torch.int32, device=tables.device)
+    if xs is None:
+        xs = torch.empty(k + 1, dtype=torch.int32, device=tables.device)
+    ws_t, ws_n = _ws(dp_workspace_bytes(h, w, k, b), tables.device, ws)
+    rc = lib().fhtp_polyline_dp(tables.data_ptr(), h, w, k, b, _ptr(ws_t), ws_n,
+                                score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
+    _check(rc, "polyline_dp")
+    return score, xs
+
+
+def detect_polyline(img, k: int, bend: Optional[int] = None, gamma: Optional[float] = None,
+                    ws=None, score=None, xs=None, stream=None):
+    """The whole detector on a device image: (score, xs) as device tensors."""
+    torch = _torch()
+    _require_device(img, "img")
+    h, w = img.shape
+    dt = _dtype_code(img)
+    b = make_bend(bend, gamma)
+    if score is None:
+        score = torch.empty(1, dtype=torch.int32, device=img.device)
+    if xs is None:
+        xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
+    ws_t, ws_n = _ws(detect_workspace_bytes(dt, h, w, k, b), img.device, ws)
+    rc = lib().fhtp_detect_polyline(img.data_ptr(), dt, h, w, k, b, _ptr(ws_t), ws_n,
+                                    score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
+    _check(rc, "detect_polyline")
+    return score, xs

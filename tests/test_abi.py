@@ -1,0 +1,145 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry point,
+and rejects invalid requests on the host before touching the GPU.
+
+No compute call here passes validation, so nothing is ever enqueued.
+"""
+
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1912_01884_amd import fhtp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fhtp.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fhtp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = fhtp.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in fhtp.h but not exported"
+    assert set(names) == set(fhtp.EXPORTED)
+    assert "gfx950" in fhtp.version()
+
+
+def test_error_strings():
+    for code in range(0, -10, -1):
+        assert fhtp.strerror(code) != "unknown error"
+    assert fhtp.strerror(-99) == "unknown error"
+
+
+@pytest.mark.parametrize("h,w,k", [(64, 64, 4), (1024, 1024, 16), (4096, 4096, 32), (8, 1, 8),
+                                   (2048, 300, 4)])
+def test_table_shape_matches_oracle(orc, h, w, k):
+    assert fhtp.table_shape(h, w, k) == orc.table_shape(h, w, k)
+
+
+BAD_SHAPES = [
+    (0, 8, 1), (8, 0, 1), (8, 8, 0), (-8, 8, 1),
+    (12, 8, 4),            # n = 3
+    (12, 8, 5),            # k does not divide h
+    (4096, 8, 2),          # n = 2048 > 1024
+    (64, (1 << 20) + 1, 4),  # w too wide
+]
+
+
+@pytest.mark.parametrize("h,w,k", BAD_SHAPES)
+def test_bad_shapes_rejected(h, w, k):
+    with pytest.raises(fhtp.FhtpError) as e:
+        fhtp.table_shape(h, w, k)
+    assert e.value.code == fhtp.ERR_DIMS
+    b = fhtp.make_bend(1)
+    for q in (lambda: fhtp.fht_workspace_bytes(0, h, w, k),
+              lambda: fhtp.dp_workspace_bytes(h, w, k, b),
+              lambda: fhtp.detect_workspace_bytes(0, h, w, k, b)):
+        with pytest.raises(fhtp.FhtpError) as e:
+            q()
+        assert e.value.code == fhtp.ERR_DIMS
+
+
+def test_overflow_and_dtype_rejected():
+    b = fhtp.make_bend(1)
+    with pytest.raises(fhtp.FhtpError) as e:
+        fhtp.detect_workspace_bytes(1, 65536, 4, 65536, b)  # 65536 * 65535 >= 2^31
+    assert e.value.code == fhtp.ERR_OVERFLOW
+    assert fhtp.detect_workspace_bytes(1, 32768, 4, 32768, b) > 0  # just below the limit
+    with pytest.raises(fhtp.FhtpError) as e:
+        fhtp.detect_workspace_bytes(2, 64, 64, 4, b)
+    assert e.value.code == fhtp.ERR_DTYPE
+
+
+@pytest.mark.parametrize("bend", [fhtp.Bend(0, -1, 0.0), fhtp.Bend(2, 1, 0.0),
+                                  fhtp.Bend(1, 0, -0.1), fhtp.Bend(1, 0, float("nan")),
+                                  fhtp.Bend(1, 0, float("inf"))])
+def test_bad_bend_rejected(bend):
+    with pytest.raises(fhtp.FhtpError) as e:
+        fhtp.dp_workspace_bytes(64, 64, 4, bend)
+    assert e.value.code == fhtp.ERR_BEND
+
+
+def test_validation_matches_oracle(orc):
+    """Both implementations reject the same shapes with the same codes."""
+    import oracle
+    for (h, w, k) in BAD_SHAPES[:7]:
+        img = np.zeros((max(h, 1), max(w, 1)), np.uint8)
+        rc_o = orc.L.oracle_detect_polyline(img.ctypes.data, 0, h, w, k, 0, 1, 0.0,
+                                            np.zeros(1, np.int32).ctypes.data_as(
+                                                C.POINTER(C.c_int32)),
+                                            np.zeros(64, np.int32).ctypes.data_as(
+                                                C.POINTER(C.c_int32)))
+        with pytest.raises(fhtp.FhtpError) as e:
+            fhtp.detect_workspace_bytes(0, h, w, k, fhtp.make_bend(1))
+        assert e.value.code == rc_o == oracle.ERR_DIMS
+
+
+def test_workspace_sizes_cover_the_buffers():
+    h, w, k = 4096, 4096, 32
+    n = h // k
+    b = fhtp.make_bend(8)
+    tables = k * (2 * n - 1) * (w + n) * 4
+    backptr = (k - 1) * (2 * n - 1) * w  # uint8 back-pointers for D <= 256
+    planes = 2 * (2 * n - 1) * w * 4
+    dp = fhtp.dp_workspace_bytes(h, w, k, b)
+    assert dp >= backptr + planes
+    det = fhtp.detect_workspace_bytes(1, h, w, k, b)
+    assert det >= dp + tables
+    assert fhtp.fht_workspace_bytes(1, h, w, k) == 0
+    # bands of 512 rows need sub-block scratch and uint16 back-pointers
+    assert fhtp.fht_workspace_bytes(0, 2048, 1000, 4) == (2048 // 128) * 2 * 128 * 1512 * 4
+    assert fhtp.dp_workspace_bytes(2048, 1000, 4, b) >= 3 * 1023 * 1000 * 2
+
+
+def test_compute_calls_validate_before_launch():
+    L = fhtp.lib()
+    b = fhtp.make_bend(1)
+    dummy = C.c_void_p(256)  # never dereferenced: every call below fails validation
+    i32 = C.c_void_p(256)
+    assert L.fhtp_fht_bands(None, 0, 64, 64, 4, i32, None, 0, None) == fhtp.ERR_NULL
+    assert L.fhtp_fht_bands(dummy, 0, 64, 64, 3, i32, None, 0, None) == fhtp.ERR_DIMS
+    assert L.fhtp_fht_bands(dummy, 5, 64, 64, 4, i32, None, 0, None) == fhtp.ERR_DTYPE
+    # tall bands need scratch: a missing or short workspace is refused
+    assert L.fhtp_fht_bands(dummy, 0, 1024, 64, 4, i32, None, 0, None) == fhtp.ERR_NULL
+    assert L.fhtp_fht_bands(dummy, 0, 1024, 64, 4, i32, dummy, 16, None) == fhtp.ERR_WORKSPACE
+    assert L.fhtp_polyline_dp(i32, 64, 64, 4, b, None, 0, i32, i32, None) == fhtp.ERR_NULL
+    assert L.fhtp_polyline_dp(i32, 64, 64, 4, b, dummy, 1, i32, i32, None) == fhtp.ERR_WORKSPACE
+    need = fhtp.dp_workspace_bytes(64, 64, 4, b)
+    assert L.fhtp_polyline_dp(i32, 64, 64, 4, b, C.c_void_p(256 + 8), need, i32, i32,
+                              None) == fhtp.ERR_WORKSPACE  # misaligned
+    assert L.fhtp_polyline_dp(i32, 64, 64, 4, fhtp.Bend(0, -2, 0.0), dummy, need, i32, i32,
+                              None) == fhtp.ERR_BEND
+    assert L.fhtp_detect_polyline(dummy, 0, 64, 64, 4, b, dummy, 1, i32, None,
+                                  None) == fhtp.ERR_NULL
+    assert L.fhtp_detect_polyline(dummy, 1, 65536, 4, 65536, b, dummy, 1, i32, i32,
+                                  None) == fhtp.ERR_OVERFLOW

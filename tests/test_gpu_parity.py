@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Everything is integer, so the bar is exact equality: band tables element by
+element, and the best score with its vertices x_0..x_k.  Inputs are the seeded
+synthetic configurations plus edge cases (one-row bands, images narrower than
+a band, single bands, tall two-pass bands, tie-heavy and saturated images,
+every kind of bend window).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection, outside per-test time limits)
+
+import synth
+from tests.gpu_util import announce, host, require_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1912_01884_amd import fhtp
+    return fhtp
+
+
+def _rng(seed):
+    return np.random.default_rng([191201884, 99, seed])
+
+
+def _img(h, w, dtype, seed, maxval=None):
+    top = np.iinfo(dtype).max if maxval is None else maxval
+    return _rng(seed).integers(0, top + 1, size=(h, w)).astype(dtype)
+
+
+TABLE_CASES = [
+    # (h, w, k, dtype, values)
+    (8, 1, 8, np.uint8, None),        # n = 1
+    (8, 5, 4, np.uint8, None),        # n = 2
+    (16, 3, 1, np.uint8, None),       # w < n
+    (64, 64, 1, np.uint16, None),
+    (96, 40, 3, np.uint8, None),      # n = 32
+    (128, 100, 1, np.uint16, None),   # n = 128, one band
+    (256, 50, 1, np.uint8, None),     # n = 256: two-pass
+    (512, 33, 1, np.uint16, None),    # n = 512
+    (2048, 70, 2, np.uint8, None),    # n = 1024
+    (256, 700, 2, np.uint8, None),    # several tiles per band
+    (512, 900, 4, np.uint16, "sat"),  # saturated
+    (64, 2000, 2, np.uint8, "sat"),
+]
+
+
+@pytest.mark.parametrize("h,w,k,dtype,vals", TABLE_CASES,
+                         ids=[f"{c[0]}x{c[1]}k{c[2]}{np.dtype(c[3]).name}{c[4] or ''}"
+                              for c in TABLE_CASES])
+def test_tables_small(dev, F, orc, h, w, k, dtype, vals):
+    img = np.full((h, w), np.iinfo(dtype).max, dtype) if vals == "sat" else _img(h, w, dtype, h + w)
+    want = orc.fht_bands(img, k)
+    announce(f"fht_bands {h}x{w} k={k} {np.dtype(dtype).name}")
+    got = host(F.fht_bands(to_device(img, dev), k))
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2", "C3"])
+def test_tables_configs(dev, F, orc, cfg):
+    s = synth.make_config(cfg)
+    want = orc.fht_bands(s.image, s.k)
+    announce(f"fht_bands {cfg}")
+    got = host(F.fht_bands(to_device(s.image, dev), s.k))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2", "C3"])
+def test_detect_configs(dev, F, orc, cfg):
+    s = synth.make_config(cfg)
+    want_s, want_x = orc.detect_polyline(s.image, s.k, bend=s.bend)
+    announce(f"detect {cfg} B={s.bend}")
+    sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, bend=s.bend)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
+@pytest.mark.parametrize("B", [0, 1, 2, 5, 8, 16, 17, 29, 30, 100])
+def test_detect_c1_every_window_kind(dev, F, orc, B):
+    s = synth.make_c1()
+    want_s, want_x = orc.detect_polyline(s.image, s.k, bend=B)
+    announce(f"detect C1 B={B}")
+    sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, bend=B)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
+@pytest.mark.parametrize("gamma", [0.0, 0.05, 0.2, math.radians(10), 1.0, math.pi / 2, 2.0])
+def test_detect_angle_bound(dev, F, orc, gamma):
+    for cfg in ("C1", "C2"):
+        s = synth.make_config(cfg)
+        want_s, want_x = orc.detect_polyline(s.image, s.k, gamma=gamma)
+        announce(f"detect {cfg} gamma={gamma}")
+        sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, gamma=gamma)
+        assert int(host(sc)[0]) == want_s
+        assert host(xs).tolist() == want_x.tolist()
+
+
+EDGE = [
+    # (h, w, k, dtype, maxval, B)
+    (8, 1, 8, np.uint8, 3, 0),        # n = 1, w = 1
+    (8, 5, 4, np.uint8, 3, 1),        # n = 2
+    (16, 3, 1, np.uint8, 3, 0),       # k = 1, w < n
+    (16, 40, 1, np.uint16, None, 2),  # k = 1
+    (32, 7, 2, np.uint8, 3, 3),       # w < n
+    (64, 64, 4, np.uint8, 0, 1),      # all zero
+    (64, 64, 4, np.uint8, 1, 1),      # zeros and ones: ties everywhere
+    (128, 130, 4, np.uint8, 3, 2),
+    (256, 300, 8, np.uint16, None, 4),
+    (512, 200, 2, np.uint8, 3, 5),    # n = 256, two-pass FHT, uint16 back-pointers
+    (2048, 300, 4, np.uint8, None, 4),  # n = 512
+    (1024, 90, 1, np.uint8, None, 3),   # n = 1024, single band
+    (200 * 4, 129, 200, np.uint8, 2, 0),  # n = 4, many bands
+]
+
+
+@pytest.mark.parametrize("h,w,k,dtype,maxval,B", EDGE,
+                         ids=[f"{c[0]}x{c[1]}k{c[2]}B{c[5]}" for c in EDGE])
+def test_detect_edges(dev, F, orc, h, w, k, dtype, maxval, B):
+    img = _img(h, w, dtype, 7 * h + w, maxval)
+    want_s, want_x = orc.detect_polyline(img, k, bend=B)
+    announce(f"detect edge {h}x{w} k={k} B={B}")
+    sc, xs = F.detect_polyline(to_device(img, dev), k, bend=B)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
+def test_saturated_image(dev, F, orc):
+    img = np.full((256, 301), 255, np.uint8)
+    announce("detect saturated 256x301")
+    sc, xs = F.detect_polyline(to_device(img, dev), 8, bend=2)
+    assert int(host(sc)[0]) == 255 * 256
+    assert not host(xs).any()
+    img16 = np.full((4096, 64), 65535, np.uint16)
+    announce("detect saturated u16 4096x64")
+    sc, xs = F.detect_polyline(to_device(img16, dev), 32, bend=8)
+    assert int(host(sc)[0]) == 65535 * 4096
+    assert not host(xs).any()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_detect_random_tiny(dev, F, orc, seed):
+    rng = _rng(500 + seed)
+    n = int(rng.choice([1, 2, 4, 8, 16]))
+    k = int(rng.integers(1, 6))
+    w = int(rng.integers(1, 70))
+    B = int(rng.integers(0, 2 * n + 1))
+    img = rng.integers(0, 4, size=(n * k, w)).astype(np.uint8)
+    want_s, want_x = orc.detect_polyline(img, k, bend=B)
+    announce(f"detect tiny seed={seed} {n * k}x{w} k={k} B={B}")
+    sc, xs = F.detect_polyline(to_device(img, dev), k, bend=B)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
+def test_polyline_dp_on_oracle_tables(dev, F, orc):
+    s = synth.make_c2()
+    tables = orc.fht_bands(s.image, s.k)
+    want_s, want_x = orc.polyline_dp(tables, s.h, s.w, s.k, bend=s.bend)
+    announce("polyline_dp C2 on oracle tables")
+    sc, xs = F.polyline_dp(to_device(tables, dev), s.h, s.w, s.k, bend=s.bend)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
+def test_repeat_runs_identical(dev, F):
+    s = synth.make_c2()
+    img = to_device(s.image, dev)
+    announce("determinism C2")
+    t1 = host(F.fht_bands(img, s.k))
+    t2 = host(F.fht_bands(img, s.k))
+    assert np.array_equal(t1, t2)
+    r1 = [host(t) for t in F.detect_polyline(img, s.k, bend=s.bend)]
+    r2 = [host(t) for t in F.detect_polyline(img, s.k, bend=s.bend)]
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+
+
+@pytest.mark.parametrize("j", range(0, 256, 16))
+def test_detect_mixed_batch_images(dev, F, orc, j):
+    """Images of the mixed-size batch workload (h 128..2048, w 256..2048, k 4..16)."""
+    s = synth.make_c4_image(j)
+    want_s, want_x = orc.detect_polyline(s.image, s.k, bend=s.bend)
+    announce(f"detect mixed image {j}: {s.h}x{s.w} k={s.k}")
+    sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, bend=s.bend)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
