@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 
 #include "fhtp_internal.h"
@@ -52,8 +53,21 @@ int pixels(fhtp_dtype dtype, int h) {
     return FHTP_OK;
 }
 
+// Displacements per thread of the fixed-window DP step: 8 gives twice the
+// waves of 16 at the cost of more halo loads (from cache); FHTP_DP_DC overrides.
+int dp_chunk(const fhtp::Geometry& g) {
+    const char* env = std::getenv("FHTP_DP_DC");
+    if (env) {
+        const int v = std::atoi(env);
+        if (v == 8 || v == 16) return v;
+    }
+    const long long threads16 = (long long)g.w * ((g.D + 15) / 16);
+    return threads16 < 256LL * 4 * 64 * 2 ? 8 : 16;
+}
+
 int plan(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
     pl->a16 = g.D > 256;
+    pl->dc = dp_chunk(g);
     pl->bound = 0;
     pl->tan_gamma = 0.0;
     if (b.mode == 0) {
@@ -90,7 +104,7 @@ DpLayout dp_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, size_t base)
     L.v1 = align_up(L.v0 + fhtp::dp_plane_bytes(g));
     L.a = align_up(L.v1 + fhtp::dp_plane_bytes(g));
     L.key = align_up(L.a + fhtp::dp_backptr_bytes(g, pl.a16));
-    L.win = align_up(L.key + sizeof(unsigned long long));
+    L.win = align_up(L.key + fhtp::dp_key_count(g) * sizeof(unsigned long long));
     L.end = align_up(L.win + 2 * (size_t)g.D * sizeof(int32_t));
     return L;
 }

@@ -20,18 +20,45 @@
 // back-pointer A_{i+1}(x', d).  Cells whose successor column leaves the image
 // are never written; readers mask them by the same rule instead.
 //
-// The last step (i = 0) writes no plane: each workgroup reduces its cells to a
-// packed key ((V + 1) << 32 | ~(x*D + r)) whose maximum is the best score with
-// the smallest (x, d) on ties, and merges it with one 64-bit atomic max.  A
-// single thread then follows the back-pointers (k-1 dependent loads).
+// The last step (i = 0) writes neither V_0 nor A_1: each workgroup reduces its
+// cells to a packed key ((V + 1) << 32 | ~(x*D + r)) whose maximum is the best
+// score with the smallest (x, d) on ties, and merges it with one 64-bit atomic
+// max.  The workgroup that finishes last then walks the back-pointers with one
+// wave (eq. (5)): the first successor is re-derived from V_1, and later ones
+// are read two bands per memory round trip by loading every candidate of the
+// next band speculatively.
 #include "fhtp_internal.h"
 
 namespace fhtp {
 namespace {
 
-constexpr int kDC = 16;        // displacements per thread
 constexpr int kWaves = 4;      // waves per workgroup, one displacement chunk each
 constexpr int kMaxFixedB = 16; // largest bend bound with a register-window kernel
+constexpr int kDCGeneric = 16; // displacements per thread in the scanning kernels
+
+// Everything a step kernel needs; passed by value.
+struct StepArgs {
+    const int32_t* vin;  // V_{i+1} (or the table H_{k-1}), rows d'+n-1
+    int vin_pitch;
+    const int32_t* htab;  // H_i
+    int h_pitch;
+    int32_t* vout;  // V_i (not written on the last step)
+    int v_pitch;
+    void* aout;  // A_{i+1} plane (not written on the last step)
+    int a_pitch;
+    int n, w;
+    int bound;           // mode-0 bound (generic kernel)
+    const int32_t* win;  // mode-1 windows lo[D], hi[D] (generic kernel) or null
+    int full;            // windows cover every displacement
+    // last step: one packed key per workgroup (the walk kernel reduces them)
+    unsigned long long* key;
+    int n_keys;
+    const void* a_base;  // plane j holds A_{j+2}, j = 0 .. k-3 (A_1 comes from V_1)
+    size_t a_plane;
+    int k;
+    int32_t* score;
+    int32_t* xs;
+};
 
 __device__ __forceinline__ unsigned long long pack_key(int val, int x, int r, int D) {
     const unsigned int lin = (unsigned int)x * (unsigned int)D + (unsigned int)r;
@@ -47,68 +74,221 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-// Block-wide max of v, merged into *key by thread 0.
-__device__ __forceinline__ void block_key_max(unsigned long long v, unsigned long long* key) {
+// V_{i+1}(x', d') with the feasibility mask: zero-based row r' = d' + n - 1.
+// The load is unconditional (masked lanes read element 0, which always
+// exists) so that every load of a thread can be in flight at once.
+__device__ __forceinline__ int load_v(const int32_t* __restrict__ vin, int pitch, int xp, int dp,
+                                      int n, int w) {
+    const int r = dp + n - 1;
+    const bool ok = (unsigned)xp < (unsigned)w && (unsigned)r < (unsigned)(2 * n - 1) &&
+                    (unsigned)(xp + dp) < (unsigned)w;
+    const unsigned int off = ok ? (unsigned int)r * (unsigned int)pitch + (unsigned int)xp : 0u;
+    const int v = vin[off];
+    return ok ? v : -1;
+}
+
+// Admissible successors of displacement d: [lo, hi] in displacement units.
+__device__ __forceinline__ void window_of(const StepArgs& a, int d, int& lo, int& hi) {
+    const int n = a.n;
+    if (a.full) {
+        lo = -(n - 1);
+        hi = n - 1;
+    } else if (a.win) {
+        lo = a.win[d + n - 1];
+        hi = a.win[2 * n - 1 + d + n - 1];
+    } else {
+        lo = max(d - a.bound, -(n - 1));
+        hi = min(d + a.bound, n - 1);
+    }
+}
+
+// H_i(x' - d, d) for one output cell, 0 where the cell does not exist
+// (unconditional load, as load_v).
+__device__ __forceinline__ int load_h(const StepArgs& a, int xp, int d) {
+    const int r = d + a.n - 1;
+    const int x = xp - d;
+    const bool ok = (unsigned)xp < (unsigned)a.w && (unsigned)r < (unsigned)(2 * a.n - 1) &&
+                    (unsigned)x < (unsigned)a.w;
+    const unsigned int off = ok ? (unsigned int)r * (unsigned int)a.h_pitch + (unsigned int)x : 0u;
+    const int v = a.htab[off];
+    return ok ? v : 0;
+}
+
+// One output cell (x' = xp, displacement d) with range maximum m reached at row ra.
+template <typename AT>
+__device__ __forceinline__ void emit(const StepArgs& a, int m, int ra, int hval, int xp, int d,
+                                     unsigned long long& best) {
+    const int n = a.n, w = a.w;
+    const int D = 2 * n - 1;
+    const int r = d + n - 1;
+    if (xp >= w || r >= D) return;
+    const bool last = a.key != nullptr;
+    if (!last)
+        static_cast<AT*>(a.aout)[(unsigned int)r * (unsigned int)a.a_pitch + (unsigned int)xp] =
+            (AT)(ra < 0 ? 0 : ra);
+    const int x = xp - d;
+    if (x < 0 || x >= w) return;
+    const int val = m >= 0 ? hval + m : -1;
+    if (last) {
+        const unsigned long long kk = pack_key(val, x, r, D);
+        best = kk > best ? kk : best;
+    } else {
+        a.vout[(unsigned int)r * (unsigned int)a.v_pitch + (unsigned int)x] = val;
+    }
+}
+
+// Walk of eq. (5) by one full wave: reduce the workgroup keys of the last
+// step, then follow the back-pointers.  The walk is a chain of dependent
+// loads, so every load is unconditional (clamped index, result masked) and
+// the loads of one round trip are all issued before the first is used.
+template <typename AT>
+__global__ __launch_bounds__(64) void walk(StepArgs a) {
+    const int lane = threadIdx.x;
+    const int n = a.n, w = a.w, k = a.k;
+    const int D = 2 * n - 1;
+    unsigned long long kv = 0;
+    for (int q0 = 0; q0 < a.n_keys; q0 += 64 * 8) {
+        unsigned long long t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 64 + lane;
+            t[u] = a.key[q < a.n_keys ? q : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) kv = t[u] > kv ? t[u] : kv;
+    }
+    kv = wave_max_u64(kv);
+    const unsigned int lin = 0xffffffffu - (unsigned int)(kv & 0xffffffffull);
+    const unsigned int xu = lin / (unsigned int)D;
+    int x = (int)xu;
+    int r = (int)(lin % (unsigned int)D);
+    if ((kv >> 32) == 0 || xu >= (unsigned int)w) {
+        if (lane == 0) *a.score = -1;
+        return;
+    }
+    if (lane == 0) a.xs[0] = x;
+    if (k >= 2) {
+        // First successor from V_1: the smallest d' of the window reaching its maximum.
+        const int x1 = x + r - (n - 1);
+        if (x1 < 0 || x1 >= w) {
+            if (lane == 0) *a.score = -1;
+            return;
+        }
+        int lo, hi;
+        window_of(a, r - (n - 1), lo, hi);
+        unsigned long long bestk = 0;
+        for (int base = lo; base <= hi; base += 64) {
+            const int dp = base + lane;
+            const int v = load_v(a.vin, a.vin_pitch, x1, dp, n, w);
+            const unsigned long long kk =
+                dp <= hi ? ((unsigned long long)(unsigned int)(v + 2) << 32) |
+                               (unsigned long long)(0xffffffffu - (unsigned int)(dp + n - 1))
+                         : 0ull;
+            const unsigned long long m = wave_max_u64(kk);
+            bestk = m > bestk ? m : bestk;
+        }
+        const int r1 = (int)(0xffffffffu - (unsigned int)(bestk & 0xffffffffull));
+        if (lane == 0) a.xs[1] = x1;
+        x = x1;
+        r = r1;
+        // Later successors from the stored planes, two bands per round trip:
+        // with link i known, read A_{i+1}(x_{i+1}, d_i) and, for every possible
+        // d_{i+1} (lane-strided), A_{i+2}(x_{i+1} + d_{i+1}, d_{i+1}).
+        const AT* A = static_cast<const AT*>(a.a_base);
+        const unsigned int pitch = (unsigned int)a.a_pitch;
+        int i = 1;
+        while (i + 1 < k) {
+            const int xn = x + r - (n - 1);
+            if (xn < 0 || xn >= w || r < 0 || r >= D) {
+                if (lane == 0) *a.score = -1;
+                return;
+            }
+            const AT* Pi = A + (size_t)(i - 1) * a.a_plane;
+            const int rn = Pi[(unsigned int)r * pitch + (unsigned int)xn];
+            const bool two = (i + 2 < k) && D <= 256;
+            int spec[4];
+            if (two) {
+                const AT* Pn = A + (size_t)i * a.a_plane;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c = lane + 64 * j;
+                    const int xc = xn + c - (n - 1);
+                    const bool ok = c < D && xc >= 0 && xc < w;
+                    const int v = Pn[ok ? (unsigned int)c * pitch + (unsigned int)xc : 0u];
+                    spec[j] = ok ? v : 0;
+                }
+            }
+            if (rn >= D) {
+                if (lane == 0) *a.score = -1;
+                return;
+            }
+            if (lane == 0) a.xs[i + 1] = xn;
+            if (two) {
+                const int xnn = xn + rn - (n - 1);
+                if (xnn < 0 || xnn >= w) {
+                    if (lane == 0) *a.score = -1;
+                    return;
+                }
+                const int slot = rn >> 6;
+                const int mine = slot == 0 ? spec[0] : slot == 1 ? spec[1] : slot == 2 ? spec[2] : spec[3];
+                const int r2 = __shfl(mine, rn & 63, 64);
+                if (lane == 0) a.xs[i + 2] = xnn;
+                x = xnn;
+                r = r2;
+                i += 2;
+            } else {
+                x = xn;
+                r = rn;
+                i += 1;
+            }
+        }
+        if (r < 0 || r >= D) {
+            if (lane == 0) *a.score = -1;
+            return;
+        }
+    }
+    if (lane == 0) {
+        a.xs[k] = x + r - (n - 1);
+        *a.score = (int)(kv >> 32) - 1;
+    }
+}
+
+// Common end of the last step: the workgroup's best key goes to its slot.
+__device__ __forceinline__ void finish(const StepArgs& a, unsigned long long best) {
+    if (!a.key) return;
     __shared__ unsigned long long part[kWaves];
-    v = wave_max_u64(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) part[wave] = v;
+    best = wave_max_u64(best);
+    if (lane == 0) part[wave] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = part[0];
 #pragma unroll
         for (int q = 1; q < kWaves; ++q) m = part[q] > m ? part[q] : m;
-        atomicMax(key, m);
+        a.key[blockIdx.y * gridDim.x + blockIdx.x] = m;
     }
 }
 
-// V_{i+1}(x', d') with the feasibility mask: zero-based row r' = d' + n - 1.
-__device__ __forceinline__ int load_v(const int32_t* __restrict__ vin, int pitch, int xp, int dp,
-                                      int n, int w) {
-    const int r = dp + n - 1;
-    const bool ok = xp < w && r >= 0 && r < 2 * n - 1 && xp + dp >= 0 && xp + dp < w;
-    return ok ? vin[(size_t)r * pitch + xp] : -1;
-}
-
-// Shared tail of every step kernel: one output cell (x' = xp, displacement d)
-// with range maximum m reached at row ra.
-template <typename AT>
-__device__ __forceinline__ void emit(int m, int ra, int xp, int d, int n, int w,
-                                     const int32_t* __restrict__ htab, int h_pitch,
-                                     int32_t* __restrict__ vout, int v_pitch, AT* __restrict__ aout,
-                                     int a_pitch, bool last, unsigned long long& best) {
-    const int D = 2 * n - 1;
-    const int r = d + n - 1;
-    if (xp >= w || r >= D) return;
-    aout[(size_t)r * a_pitch + xp] = (AT)(ra < 0 ? 0 : ra);
-    const int x = xp - d;
-    if (x < 0 || x >= w) return;
-    const int val = m >= 0 ? htab[(size_t)r * h_pitch + x] + m : -1;
-    if (last) {
-        const unsigned long long kk = pack_key(val, x, r, D);
-        best = kk > best ? kk : best;
-    } else {
-        vout[(size_t)r * v_pitch + x] = val;
-    }
-}
-
-// Step with the mode-0 window [d - B, d + B] fixed at compile time.
-template <int B, typename AT>
-__global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(
-    const int32_t* __restrict__ vin, int vin_pitch, const int32_t* __restrict__ htab, int h_pitch,
-    int32_t* __restrict__ vout, int v_pitch, AT* __restrict__ aout, int a_pitch,
-    unsigned long long* __restrict__ key, int n, int w) {
+// Step with the mode-0 window [d - B, d + B] fixed at compile time; each
+// thread produces DC consecutive displacements.
+template <int B, int DC, typename AT>
+__global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(StepArgs a) {
     constexpr int L = 2 * B + 1;
-    constexpr int NV = kDC + 2 * B;
+    constexpr int NV = DC + 2 * B;
+    const int n = a.n, w = a.w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int xp = blockIdx.x * 64 + lane;
     const int chunk = blockIdx.y * kWaves + wave;
-    const int d0 = -(n - 1) + chunk * kDC;
-    const bool last = key != nullptr;
+    const int d0 = -(n - 1) + chunk * DC;
+    const bool last = a.key != nullptr;
 
+    // All loads up front: the window column of V_{i+1} and the H_i cells.
     int v[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = load_v(vin, vin_pitch, xp, d0 - B + j, n, w);
+    for (int j = 0; j < NV; ++j) v[j] = load_v(a.vin, a.vin_pitch, xp, d0 - B + j, n, w);
+    int hv[DC];
+#pragma unroll
+    for (int j = 0; j < DC; ++j) hv[j] = load_h(a, xp, d0 + j);
 
     // Suffix maxima inside window-length blocks (smallest index on ties).
     int sv[NV], si[NV];
@@ -139,100 +319,76 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(
             const bool s_wins = sv[j] >= pv;
             const int m = s_wins ? sv[j] : pv;
             const int ia = s_wins ? si[j] : pi;
-            const int ra = chunk * kDC - B + ia;  // row of d' = d0 - B + ia
-            emit<AT>(m, ra, xp, d0 + j, n, w, htab, h_pitch, vout, v_pitch, aout, a_pitch, last,
-                     best);
+            const int ra = chunk * DC - B + ia;  // row of d' = d0 - B + ia
+            emit<AT>(a, m, ra, hv[j], xp, d0 + j, best);
         }
     }
-    if (last) block_key_max(best, key);
+    (void)last;
+    finish(a, best);
 }
 
-// Step with per-displacement windows [lo(d), hi(d)] (large mode-0 bounds and
-// the angle form), scanning each window.
+// Step with per-displacement windows [lo(d), hi(d)] (large mode-0 bounds, the
+// angle form, no bound at all), scanning each window.
 template <typename AT>
-__global__ __launch_bounds__(64 * kWaves) void dp_step_generic(
-    const int32_t* __restrict__ vin, int vin_pitch, const int32_t* __restrict__ htab, int h_pitch,
-    int32_t* __restrict__ vout, int v_pitch, AT* __restrict__ aout, int a_pitch,
-    unsigned long long* __restrict__ key, int n, int w, int bound,
-    const int32_t* __restrict__ win) {
+__global__ __launch_bounds__(64 * kWaves) void dp_step_generic(StepArgs a) {
+    const int n = a.n, w = a.w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int xp = blockIdx.x * 64 + lane;
     const int chunk = blockIdx.y * kWaves + wave;
-    const int d0 = -(n - 1) + chunk * kDC;
+    const int d0 = -(n - 1) + chunk * kDCGeneric;
     const int D = 2 * n - 1;
-    const bool last = key != nullptr;
     unsigned long long best = 0;
-    for (int j = 0; j < kDC; ++j) {
-        const int d = d0 + j;
-        const int r = d + n - 1;
-        if (r >= D) break;
-        int lo, hi;
-        if (win) {
-            lo = win[r];
-            hi = win[D + r];
-        } else {
-            lo = max(d - bound, -(n - 1));
-            hi = min(d + bound, n - 1);
-        }
-        int m = load_v(vin, vin_pitch, xp, lo, n, w);
-        int ia = lo;
-        for (int dp = lo + 1; dp <= hi; ++dp) {
-            const int vv = load_v(vin, vin_pitch, xp, dp, n, w);
+    if (a.full) {
+        // Section 2.2: every d shares the maximum of the whole successor column.
+        int m = load_v(a.vin, a.vin_pitch, xp, -(n - 1), n, w);
+        int ia = -(n - 1);
+        for (int dp = -(n - 1) + 1; dp <= n - 1; ++dp) {
+            const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
             if (vv > m) {
                 m = vv;
                 ia = dp;
             }
         }
-        emit<AT>(m, ia + n - 1, xp, d, n, w, htab, h_pitch, vout, v_pitch, aout, a_pitch, last,
-                 best);
-    }
-    if (last) block_key_max(best, key);
-}
-
-// Step without a bend limit (Section 2.2): every d shares the column maximum.
-template <typename AT>
-__global__ __launch_bounds__(64 * kWaves) void dp_step_full(
-    const int32_t* __restrict__ vin, int vin_pitch, const int32_t* __restrict__ htab, int h_pitch,
-    int32_t* __restrict__ vout, int v_pitch, AT* __restrict__ aout, int a_pitch,
-    unsigned long long* __restrict__ key, int n, int w) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xp = blockIdx.x * 64 + lane;
-    const int chunk = blockIdx.y * kWaves + wave;
-    const int d0 = -(n - 1) + chunk * kDC;
-    const bool last = key != nullptr;
-    int m = load_v(vin, vin_pitch, xp, -(n - 1), n, w);
-    int ia = -(n - 1);
-    for (int dp = -(n - 1) + 1; dp <= n - 1; ++dp) {
-        const int vv = load_v(vin, vin_pitch, xp, dp, n, w);
-        if (vv > m) {
-            m = vv;
-            ia = dp;
+        for (int j = 0; j < kDCGeneric; ++j)
+            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d0 + j), xp, d0 + j, best);
+    } else {
+        for (int j = 0; j < kDCGeneric; ++j) {
+            const int d = d0 + j;
+            if (d + n - 1 >= D) break;
+            int lo, hi;
+            window_of(a, d, lo, hi);
+            int m = load_v(a.vin, a.vin_pitch, xp, lo, n, w);
+            int ia = lo;
+            for (int dp = lo + 1; dp <= hi; ++dp) {
+                const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
+                if (vv > m) {
+                    m = vv;
+                    ia = dp;
+                }
+            }
+            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d), xp, d, best);
         }
     }
-    unsigned long long best = 0;
-    for (int j = 0; j < kDC; ++j)
-        emit<AT>(m, ia + n - 1, xp, d0 + j, n, w, htab, h_pitch, vout, v_pitch, aout, a_pitch,
-                 last, best);
-    if (last) block_key_max(best, key);
+    finish(a, best);
 }
 
 // k = 1: the answer is the best masked cell of H_0.
-__global__ __launch_bounds__(64 * kWaves) void argmax_table(const int32_t* __restrict__ htab,
-                                                            int h_pitch, int n, int w,
-                                                            unsigned long long* __restrict__ key) {
+template <typename AT>
+__global__ __launch_bounds__(64 * kWaves) void argmax_table(StepArgs a) {
+    const int n = a.n, w = a.w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x = blockIdx.x * 64 + lane;
     const int chunk = blockIdx.y * kWaves + wave;
     const int D = 2 * n - 1;
     unsigned long long best = 0;
-    for (int j = 0; j < kDC; ++j) {
-        const int r = chunk * kDC + j;
+    for (int j = 0; j < kDCGeneric; ++j) {
+        const int r = chunk * kDCGeneric + j;
         const int d = r - (n - 1);
         if (r >= D || x >= w || x + d < 0 || x + d >= w) continue;
-        const unsigned long long kk = pack_key(htab[(size_t)r * h_pitch + x], x, r, D);
+        const unsigned long long kk = pack_key(a.htab[(size_t)r * a.h_pitch + x], x, r, D);
         best = kk > best ? kk : best;
     }
-    block_key_max(best, key);
+    finish(a, best);
 }
 
 // Mode-1 windows: lo(d) and hi(d) bracket every d' with n*|d'-d| <= t*(n*n + d*d').
@@ -254,74 +410,23 @@ __global__ void angle_windows(int n, double t, int32_t* __restrict__ win) {
     win[D + r] = hi;
 }
 
-__global__ void clear_key(unsigned long long* key) { *key = 0ull; }
-
-// Follows the back-pointers from the best cell of V_0 (eq. (5)).  Indices are
-// range-checked, so a corrupt key or plane ends the walk with score -1 rather
-// than an out-of-bounds read.
-template <typename AT>
-__global__ void backtrace(const unsigned long long* __restrict__ key, const AT* __restrict__ a,
-                          size_t a_plane, int a_pitch, int n, int w, int k,
-                          int32_t* __restrict__ score, int32_t* __restrict__ xs) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int D = 2 * n - 1;
-    const unsigned long long kv = *key;
-    const unsigned int lin = 0xffffffffu - (unsigned int)(kv & 0xffffffffull);
-    const unsigned int xu = lin / (unsigned int)D;
-    int x = (int)xu;
-    int r = (int)(lin % (unsigned int)D);
-    if ((kv >> 32) == 0 || xu >= (unsigned int)w) {
-        *score = -1;
-        return;
-    }
-    xs[0] = x;
-    for (int i = 0; i + 1 < k; ++i) {
-        const int x1 = x + r - (n - 1);
-        if (x1 < 0 || x1 >= w) {
-            *score = -1;
-            return;
-        }
-        xs[i + 1] = x1;
-        r = a[(size_t)i * a_plane + (size_t)r * a_pitch + x1];
-        if (r >= D) {
-            *score = -1;
-            return;
-        }
-        x = x1;
-    }
-    xs[k] = x + r - (n - 1);
-    *score = (int)(kv >> 32) - 1;
-}
-
 template <int B, typename AT>
-hipError_t launch_fixed_b(dim3 grid, hipStream_t s, const int32_t* vin, int vp, const int32_t* h,
-                          int hp, int32_t* vout, int op, AT* a, int ap,
-                          unsigned long long* key, int n, int w) {
-    hipLaunchKernelGGL((dp_step_fixed<B, AT>), grid, dim3(64 * kWaves), 0, s, vin, vp, h, hp,
-                       vout, op, a, ap, key, n, w);
-    return hipSuccess;
+void launch_fixed_b(int dc, dim3 grid, hipStream_t s, const StepArgs& a) {
+    if (dc == 8)
+        hipLaunchKernelGGL((dp_step_fixed<B, 8, AT>), grid, dim3(64 * kWaves), 0, s, a);
+    else
+        hipLaunchKernelGGL((dp_step_fixed<B, 16, AT>), grid, dim3(64 * kWaves), 0, s, a);
 }
 
 template <typename AT>
-hipError_t launch_step(const DpPlan& plan, dim3 grid, hipStream_t s, const int32_t* vin, int vp,
-                       const int32_t* h, int hp, int32_t* vout, int op, AT* a, int ap,
-                       unsigned long long* key, int n, int w, const int32_t* win) {
-    switch (plan.kind) {
-        case WindowKind::Full:
-            hipLaunchKernelGGL((dp_step_full<AT>), grid, dim3(64 * kWaves), 0, s, vin, vp, h, hp,
-                               vout, op, a, ap, key, n, w);
-            return hipSuccess;
-        case WindowKind::Generic:
-        case WindowKind::Angle:
-            hipLaunchKernelGGL((dp_step_generic<AT>), grid, dim3(64 * kWaves), 0, s, vin, vp, h,
-                               hp, vout, op, a, ap, key, n, w, plan.bound,
-                               plan.kind == WindowKind::Angle ? win : nullptr);
-            return hipSuccess;
-        case WindowKind::Fixed:
-            break;
+hipError_t launch_step(const DpPlan& plan, dim3 grid_fixed, dim3 grid_generic, hipStream_t s,
+                       const StepArgs& a) {
+    if (plan.kind != WindowKind::Fixed) {
+        hipLaunchKernelGGL((dp_step_generic<AT>), grid_generic, dim3(64 * kWaves), 0, s, a);
+        return hipSuccess;
     }
 #define FHTP_B(BB) \
-    case BB: return launch_fixed_b<BB, AT>(grid, s, vin, vp, h, hp, vout, op, a, ap, key, n, w);
+    case BB: launch_fixed_b<BB, AT>(plan.dc, grid_fixed, s, a); return hipSuccess;
     switch (plan.bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
         FHTP_B(9) FHTP_B(10) FHTP_B(11) FHTP_B(12) FHTP_B(13) FHTP_B(14) FHTP_B(15) FHTP_B(16)
@@ -335,35 +440,57 @@ hipError_t launch_dp_t(const int32_t* tables, const Geometry& g, const DpPlan& p
                        const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t s) {
     const int n = g.n, w = g.w, k = g.k, D = g.D;
     const size_t band_stride = (size_t)D * g.W;
-    const int chunks = (D + kDC - 1) / kDC;
-    dim3 grid((w + 63) / 64, (chunks + kWaves - 1) / kWaves, 1);
-    AT* a = static_cast<AT*>(buf.a);
+    const int chunks16 = (D + 15) / 16;
+    const int chunks_fixed = (D + plan.dc - 1) / plan.dc;
+    const dim3 grid_fixed((w + 63) / 64, (chunks_fixed + kWaves - 1) / kWaves, 1);
+    const dim3 grid_generic((w + 63) / 64, (chunks16 + kWaves - 1) / kWaves, 1);
+    AT* A = static_cast<AT*>(buf.a);
     const size_t a_plane = (size_t)D * g.pitch;
 
-    hipLaunchKernelGGL(clear_key, dim3(1), dim3(1), 0, s, buf.key);
+    StepArgs a{};
+    a.n = n;
+    a.w = w;
+    a.bound = plan.bound;
+    a.full = plan.kind == WindowKind::Full;
+    a.win = plan.kind == WindowKind::Angle ? buf.win : nullptr;
+    a.a_base = A;
+    a.a_plane = a_plane;
+    a.a_pitch = g.pitch;
+    a.k = k;
+    a.score = score;
+    a.xs = xs;
+    a.v_pitch = g.pitch;
+    a.h_pitch = g.W;
+
     if (plan.kind == WindowKind::Angle)
         hipLaunchKernelGGL(angle_windows, dim3((D + 255) / 256), dim3(256), 0, s, n,
                            plan.tan_gamma, buf.win);
+    a.key = buf.key;
     if (k == 1) {
-        hipLaunchKernelGGL(argmax_table, grid, dim3(64 * kWaves), 0, s, tables, g.W, n, w,
-                           buf.key);
+        a.htab = tables;
+        a.n_keys = (int)(grid_generic.x * grid_generic.y);
+        hipLaunchKernelGGL((argmax_table<AT>), grid_generic, dim3(64 * kWaves), 0, s, a);
     } else {
-        const int32_t* vin = tables + (size_t)(k - 1) * band_stride;
-        int vin_pitch = g.W;
+        a.vin = tables + (size_t)(k - 1) * band_stride;
+        a.vin_pitch = g.W;
         for (int i = k - 2; i >= 0; --i) {
             const bool last = i == 0;
-            int32_t* vout = last ? nullptr : buf.v[i & 1];
-            hipError_t e = launch_step<AT>(plan, grid, s, vin, vin_pitch,
-                                           tables + (size_t)i * band_stride, g.W, vout, g.pitch,
-                                           a + (size_t)i * a_plane, g.pitch,
-                                           last ? buf.key : nullptr, n, w, buf.win);
+            a.htab = tables + (size_t)i * band_stride;
+            a.vout = last ? nullptr : buf.v[i & 1];
+            a.aout = last ? nullptr : A + (size_t)(i - 1) * a_plane;
+            a.key = last ? buf.key : nullptr;
+            const dim3 grid = plan.kind == WindowKind::Fixed ? grid_fixed : grid_generic;
+            a.n_keys = (int)(grid.x * grid.y);
+            hipError_t e = launch_step<AT>(plan, grid_fixed, grid_generic, s, a);
             if (e != hipSuccess) return e;
-            vin = vout;
-            vin_pitch = g.pitch;
+            if (!last) {
+                a.vin = a.vout;
+                a.vin_pitch = g.pitch;
+            }
         }
+        a.key = buf.key;
     }
-    hipLaunchKernelGGL((backtrace<AT>), dim3(1), dim3(64), 0, s, buf.key, a, a_plane, g.pitch, n,
-                       w, k, score, xs);
+    hipLaunchKernelGGL((walk<AT>), dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -371,14 +498,22 @@ hipError_t launch_dp_t(const int32_t* tables, const Geometry& g, const DpPlan& p
 
 size_t dp_plane_bytes(const Geometry& g) { return (size_t)g.D * g.pitch * sizeof(int32_t); }
 
+size_t dp_key_count(const Geometry& g) {
+    // workgroups of the last step at 8 displacements per thread (the largest grid)
+    const size_t chunks = (size_t)(g.D + 7) / 8;
+    return (size_t)((g.w + 63) / 64) * ((chunks + kWaves - 1) / kWaves);
+}
+
 size_t dp_backptr_bytes(const Geometry& g, bool a16) {
-    const size_t planes = g.k > 1 ? (size_t)(g.k - 1) : 1;
+    // Planes for A_2 .. A_{k-1}; A_1 is re-derived from V_1 during the walk.
+    const size_t planes = g.k > 2 ? (size_t)(g.k - 2) : 1;
     return planes * g.D * g.pitch * (a16 ? 2 : 1);
 }
 
 hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
                      const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream) {
-    if (plan.kind == WindowKind::Fixed && (plan.bound < 0 || plan.bound > kMaxFixedB))
+    if (plan.kind == WindowKind::Fixed &&
+        (plan.bound < 0 || plan.bound > kMaxFixedB || (plan.dc != 8 && plan.dc != 16)))
         return hipErrorInvalidValue;
     if (plan.a16) return launch_dp_t<uint16_t>(tables, g, plan, buf, score, xs, stream);
     return launch_dp_t<uint8_t>(tables, g, plan, buf, score, xs, stream);

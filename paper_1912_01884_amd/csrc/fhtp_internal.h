@@ -37,17 +37,19 @@ struct DpPlan {
     int bound;          // mode 0 shift bound
     double tan_gamma;   // mode 1
     bool a16;           // back-pointers stored as uint16 (D > 256) instead of uint8
+    int dc;             // displacements per thread in the fixed-window step (8 or 16)
 };
 
 struct DpBuffers {
     int32_t* v[2];            // ping-pong value planes [D][pitch]
-    void* a;                  // back-pointer planes [k-1][D][pitch]
-    unsigned long long* key;  // packed argmax key
+    void* a;                  // back-pointer planes [k-2][D][pitch]
+    unsigned long long* key;  // packed argmax keys, one per workgroup of the last step
     int32_t* win;             // angle windows lo[D], hi[D]
 };
 
 size_t dp_plane_bytes(const Geometry& g);
 size_t dp_backptr_bytes(const Geometry& g, bool a16);
+size_t dp_key_count(const Geometry& g);
 hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
                      const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream);
 
