@@ -66,6 +66,59 @@ def cpu_baseline(img, k, bend, seconds):
             "sample": f"{runs} full detection(s) of the {h}x{w} image, {el:.1f} s"}
 
 
+def mixed_batch(n_images, reps, dev, stream):
+    """The mixed-size workload: images/s one detection at a time vs one batched call.
+
+    Both paths get prebuilt arguments and preallocated workspaces, so the
+    comparison is between the library's two entry points, not Python overhead.
+    """
+    import ctypes as C
+
+    import torch
+
+    import synth
+    from paper_1912_01884_amd import fhtp
+
+    batch = synth.make_c4_batch(n_images)
+    imgs = [torch.from_numpy(s.image).to(dev) for s in batch]
+    jobs, keep = fhtp.make_jobs(imgs, [s.k for s in batch], bends=[s.bend for s in batch])
+    L = fhtp.lib()
+    sptr = int(stream.cuda_stream)
+    # plain path: one workspace big enough for the largest image, reused in stream order
+    single_ws = max(fhtp.detect_workspace_bytes(j.dtype, j.h, j.w, j.k, j.bend) for j in jobs)
+    ws1 = torch.empty(single_ws, dtype=torch.uint8, device=dev)
+    args1 = [(j.img, j.dtype, j.h, j.w, j.k, j.bend, C.c_void_p(ws1.data_ptr()), single_ws,
+              j.score, j.xs, C.c_void_p(sptr)) for j in jobs]
+
+    def plain():
+        for a in args1:
+            rc = L.fhtp_detect_polyline(*a)
+            if rc != 0:
+                raise RuntimeError(f"detect_polyline failed: {rc}")
+
+    arr = (fhtp.Job * len(jobs))(*jobs)
+    nb = fhtp.batch_workspace_bytes(jobs)
+    wsb = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+    def batched():
+        rc = L.fhtp_detect_batch(arr, len(jobs), C.c_void_p(wsb.data_ptr()), nb, C.c_void_p(sptr))
+        if rc != 0:
+            raise RuntimeError(f"detect_batch failed: {rc}")
+
+    plain()
+    batched()
+    torch.cuda.synchronize()
+    ms_plain = time_events(plain, reps, stream)
+    ms_batch = time_events(batched, reps, stream)
+    mpix = sum(s.h * s.w for s in batch) / 1e6
+    return {"images": n_images, "mpix_per_batch": round(mpix, 2),
+            "plain_images_per_s": round(n_images / (ms_plain * 1e-3), 1),
+            "batched_images_per_s": round(n_images / (ms_batch * 1e-3), 1),
+            "plain_ms": round(ms_plain, 3), "batched_ms": round(ms_batch, 3),
+            "speedup": round(ms_plain / ms_batch, 2),
+            "batched_mpix_per_s": round(mpix / (ms_batch * 1e-3), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +127,9 @@ def main():
     ap.add_argument("--config", default="C3", choices=["C1", "C2", "C3"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-images", type=int, default=256,
+                    help="images of the mixed-size workload timed batched vs one at a time "
+                         "(0 skips it)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -165,6 +221,8 @@ def main():
                      "achieved": round(fht_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(fht_gbps / HBM_PEAK_GBPS, 4), "traffic": None},
     }
+    if args.batch_images > 0:
+        line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s.image, k, B, args.cpu_seconds)
     res = (int(score.cpu()[0]), xs.cpu().numpy().tolist())

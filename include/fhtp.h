@@ -143,6 +143,31 @@ int fhtp_detect_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend
 int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
                          void* ws, size_t ws_bytes, int32_t* score, int32_t* xs, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Many detections in one call: images of different h, w, k, pixel type and
+ * bend restriction.  The result of every job is bit-identical to
+ * fhtp_detect_polyline on that job alone; images of the same band height
+ * share FHT launches and images of the same window class share every DP step
+ * launch, so a batch costs a few launches per band step instead of a few per
+ * image and step.
+ *
+ * jobs:  HOST array of `count` descriptors (read during the call only); the
+ *        pointers inside are device pointers as in fhtp_detect_polyline.
+ * ws:    device scratch, fhtp_batch_workspace_bytes(...) bytes.
+ * Errors: the first invalid job's code; nothing is enqueued in that case.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const void* img;  /* device, [h][w] of `dtype` */
+    int32_t dtype;    /* fhtp_dtype */
+    int32_t h, w, k;
+    fhtp_bend bend;
+    int32_t* score;   /* device, 1 int32 */
+    int32_t* xs;      /* device, k+1 int32 */
+} fhtp_job;
+
+int fhtp_batch_workspace_bytes(const fhtp_job* jobs, int count, size_t* bytes);
+int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

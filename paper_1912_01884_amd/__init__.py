@@ -10,5 +10,6 @@ hand-written HIP kernels for gfx950 behind the C ABI in include/fhtp.h;
 from . import fhtp  # noqa: F401
 from .fhtp import (  # noqa: F401
     Bend, FhtpError, make_bend, table_shape, fht_bands, polyline_dp, detect_polyline,
-    fht_workspace_bytes, dp_workspace_bytes, detect_workspace_bytes,
+    fht_workspace_bytes, dp_workspace_bytes, detect_workspace_bytes, detect_batch,
+    batch_workspace_bytes, Job,
 )

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <string>
+#include <vector>
 
 #include "fhtp_internal.h"
 
@@ -95,14 +96,13 @@ int plan(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
 }
 
 struct DpLayout {
-    size_t v0, v1, a, key, win, end;
+    size_t v, a, key, win, end;
 };
 
 DpLayout dp_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, size_t base) {
     DpLayout L;
-    L.v0 = base;
-    L.v1 = align_up(L.v0 + fhtp::dp_plane_bytes(g));
-    L.a = align_up(L.v1 + fhtp::dp_plane_bytes(g));
+    L.v = base;  // two value planes used in turn
+    L.a = align_up(L.v + 2 * fhtp::dp_plane_bytes(g));
     L.key = align_up(L.a + fhtp::dp_backptr_bytes(g, pl.a16));
     L.win = align_up(L.key + fhtp::dp_key_count(g) * sizeof(unsigned long long));
     L.end = align_up(L.win + 2 * (size_t)g.D * sizeof(int32_t));
@@ -124,8 +124,7 @@ DetectLayout detect_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl) {
 
 fhtp::DpBuffers dp_buffers(char* ws, const DpLayout& L) {
     fhtp::DpBuffers b;
-    b.v[0] = reinterpret_cast<int32_t*>(ws + L.v0);
-    b.v[1] = reinterpret_cast<int32_t*>(ws + L.v1);
+    b.vplanes = reinterpret_cast<int32_t*>(ws + L.v);
     b.a = ws + L.a;
     b.key = reinterpret_cast<unsigned long long*>(ws + L.key);
     b.win = reinterpret_cast<int32_t*>(ws + L.win);
@@ -269,6 +268,81 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
     if (rc != FHTP_OK) return rc;
     return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(base, L.dp), score, xs, s),
                       "detect_polyline/dp");
+}
+
+namespace {
+
+// Validated job with its workspace share.
+struct BatchEntry {
+    fhtp::Geometry g;
+    fhtp::DpPlan pl;
+    DetectLayout L;
+    size_t offset;
+};
+
+int plan_batch(const fhtp_job* jobs, int count, std::vector<BatchEntry>* out, size_t* total) {
+    if (!jobs && count > 0) return FHTP_ERR_NULL;
+    if (count < 0) return FHTP_ERR_DIMS;
+    out->clear();
+    out->reserve(count);
+    size_t off = 0;
+    for (int q = 0; q < count; ++q) {
+        const fhtp_job& J = jobs[q];
+        BatchEntry e;
+        if (!J.img || !J.score || !J.xs) return FHTP_ERR_NULL;
+        int rc = shape(J.h, J.w, J.k, &e.g);
+        if (rc == FHTP_OK) rc = pixels((fhtp_dtype)J.dtype, J.h);
+        if (rc == FHTP_OK) rc = plan(e.g, J.bend, &e.pl);
+        if (rc != FHTP_OK) {
+            char buf[64];
+            std::snprintf(buf, sizeof(buf), "job %d", q);
+            g_detail = buf;
+            return rc;
+        }
+        e.L = detect_layout(e.g, e.pl);
+        e.offset = off;
+        off = align_up(off + e.L.dp.end);
+        out->push_back(e);
+    }
+    *total = off;
+    return FHTP_OK;
+}
+
+}  // namespace
+
+int fhtp_batch_workspace_bytes(const fhtp_job* jobs, int count, size_t* bytes) {
+    if (!bytes) return FHTP_ERR_NULL;
+    std::vector<BatchEntry> plan_v;
+    size_t total = 0;
+    const int rc = plan_batch(jobs, count, &plan_v, &total);
+    if (rc != FHTP_OK) return rc;
+    *bytes = total;
+    return FHTP_OK;
+}
+
+int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, void* stream) {
+    std::vector<BatchEntry> plan_v;
+    size_t total = 0;
+    int rc = plan_batch(jobs, count, &plan_v, &total);
+    if (rc != FHTP_OK) return rc;
+    if (count == 0) return FHTP_OK;
+    rc = check_ws(ws, ws_bytes, total);
+    if (rc != FHTP_OK) return rc;
+    std::vector<fhtp::FhtJobSpec> fj(count);
+    std::vector<fhtp::DpJobSpec> dj(count);
+    for (int q = 0; q < count; ++q) {
+        const BatchEntry& e = plan_v[q];
+        char* base = static_cast<char*>(ws) + e.offset;
+        int32_t* tables = reinterpret_cast<int32_t*>(base + e.L.tables);
+        fj[q] = fhtp::FhtJobSpec{jobs[q].img, (int)jobs[q].dtype, e.g, tables, base + e.L.scratch};
+        dj[q] = fhtp::DpJobSpec{tables, e.g, e.pl, dp_buffers(base, e.L.dp), jobs[q].score,
+                                jobs[q].xs};
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    rc = hip_status(fhtp::launch_fht_jobs(fj.data(), count, s), "detect_batch/fht");
+    if (rc != FHTP_OK) return rc;
+    return hip_status(fhtp::launch_dp_jobs(dj.data(), count, s), "detect_batch/dp");
 }
 
 }  // extern "C"

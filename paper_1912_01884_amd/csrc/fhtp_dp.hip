@@ -22,11 +22,18 @@
 //
 // The last step (i = 0) writes neither V_0 nor A_1: each workgroup reduces its
 // cells to a packed key ((V + 1) << 32 | ~(x*D + r)) whose maximum is the best
-// score with the smallest (x, d) on ties, and merges it with one 64-bit atomic
-// max.  The workgroup that finishes last then walks the back-pointers with one
-// wave (eq. (5)): the first successor is re-derived from V_1, and later ones
-// are read two bands per memory round trip by loading every candidate of the
-// next band speculatively.
+// score with the smallest (x, d) on ties.  One wave per image then reduces the
+// keys and walks the back-pointers (eq. (5)): the first successor is re-derived
+// from V_1, and later ones are read two bands per memory round trip by loading
+// every candidate of the next band speculatively.
+//
+// Every launch takes a pack of images (jobs).  An image with k bands takes
+// part in the step launches s = 0 .. k-2 of its pack (band i = k-2-s), so a
+// batch of images of different sizes shares one launch per step instead of one
+// per image and step.
+#include <algorithm>
+#include <vector>
+
 #include "fhtp_internal.h"
 
 namespace fhtp {
@@ -35,30 +42,60 @@ namespace {
 constexpr int kWaves = 4;      // waves per workgroup, one displacement chunk each
 constexpr int kMaxFixedB = 16; // largest bend bound with a register-window kernel
 constexpr int kDCGeneric = 16; // displacements per thread in the scanning kernels
+constexpr int kPack = 32;      // images per launch (kernel-argument size)
 
-// Everything a step kernel needs; passed by value.
-struct StepArgs {
-    const int32_t* vin;  // V_{i+1} (or the table H_{k-1}), rows d'+n-1
-    int vin_pitch;
-    const int32_t* htab;  // H_i
-    int h_pitch;
-    int32_t* vout;  // V_i (not written on the last step)
-    int v_pitch;
-    void* aout;  // A_{i+1} plane (not written on the last step)
-    int a_pitch;
+// One image in one step launch.
+struct DpJob {
+    const int32_t* vin;       // V_{i+1} (or the table H_{k-1}), rows d'+n-1
+    const int32_t* htab;      // H_i
+    int32_t* vout;            // V_i (null on the image's last step)
+    void* aout;               // A_{i+1} plane (null on the last step)
+    unsigned long long* key;  // last step: one packed key per workgroup, else null
+    const int32_t* win;       // mode-1 windows lo[D], hi[D], or null
+    int vin_pitch, h_pitch, v_pitch, a_pitch;
     int n, w;
-    int bound;           // mode-0 bound (generic kernel)
-    const int32_t* win;  // mode-1 windows lo[D], hi[D] (generic kernel) or null
-    int full;            // windows cover every displacement
-    // last step: one packed key per workgroup (the walk kernel reduces them)
-    unsigned long long* key;
-    int n_keys;
-    const void* a_base;  // plane j holds A_{j+2}, j = 0 .. k-3 (A_1 comes from V_1)
+    int bound;    // mode-0 bound (scanning kernel)
+    int full;     // windows cover every displacement
+    int items_x;  // workgroups along x
+    int item0;    // first workgroup of this image in the launch
+};
+
+// CAP images per launch: 1 for a single image (small kernel arguments, which
+// are copied with every launch), kPack for batches.
+template <int CAP>
+struct DpPack {
+    DpJob job[CAP];
+    int count;
+    int total;  // workgroups in the launch
+};
+
+// One image in the walk launch.
+struct WalkJob {
+    const unsigned long long* key;  // keys of the last step (or of the k = 1 argmax)
+    const int32_t* vin;             // V_1 (the table H_1 when k = 2)
+    const void* a_base;             // plane j holds A_{j+2}, j = 0 .. k-3 (A_1 comes from V_1)
     size_t a_plane;
-    int k;
+    const int32_t* win;
     int32_t* score;
     int32_t* xs;
+    int n_keys, vin_pitch, a_pitch;
+    int n, w, k;
+    int bound, full;
 };
+
+template <int CAP>
+struct WalkPack {
+    WalkJob job[CAP];
+    int count;
+};
+
+template <int CAP>
+__device__ __forceinline__ int dp_find_job(const DpPack<CAP>& pk, int item) {
+    int j = 0;
+    if constexpr (CAP > 1)
+        for (int q = 1; q < pk.count; ++q) j = item >= pk.job[q].item0 ? q : j;
+    return j;
+}
 
 __device__ __forceinline__ unsigned long long pack_key(int val, int x, int r, int D) {
     const unsigned int lin = (unsigned int)x * (unsigned int)D + (unsigned int)r;
@@ -88,23 +125,23 @@ __device__ __forceinline__ int load_v(const int32_t* __restrict__ vin, int pitch
 }
 
 // Admissible successors of displacement d: [lo, hi] in displacement units.
-__device__ __forceinline__ void window_of(const StepArgs& a, int d, int& lo, int& hi) {
-    const int n = a.n;
-    if (a.full) {
+__device__ __forceinline__ void window_of(int n, int full, const int32_t* win, int bound, int d,
+                                          int& lo, int& hi) {
+    if (full) {
         lo = -(n - 1);
         hi = n - 1;
-    } else if (a.win) {
-        lo = a.win[d + n - 1];
-        hi = a.win[2 * n - 1 + d + n - 1];
+    } else if (win) {
+        lo = win[d + n - 1];
+        hi = win[2 * n - 1 + d + n - 1];
     } else {
-        lo = max(d - a.bound, -(n - 1));
-        hi = min(d + a.bound, n - 1);
+        lo = max(d - bound, -(n - 1));
+        hi = min(d + bound, n - 1);
     }
 }
 
 // H_i(x' - d, d) for one output cell, 0 where the cell does not exist
 // (unconditional load, as load_v).
-__device__ __forceinline__ int load_h(const StepArgs& a, int xp, int d) {
+__device__ __forceinline__ int load_h(const DpJob& a, int xp, int d) {
     const int r = d + a.n - 1;
     const int x = xp - d;
     const bool ok = (unsigned)xp < (unsigned)a.w && (unsigned)r < (unsigned)(2 * a.n - 1) &&
@@ -116,7 +153,7 @@ __device__ __forceinline__ int load_h(const StepArgs& a, int xp, int d) {
 
 // One output cell (x' = xp, displacement d) with range maximum m reached at row ra.
 template <typename AT>
-__device__ __forceinline__ void emit(const StepArgs& a, int m, int ra, int hval, int xp, int d,
+__device__ __forceinline__ void emit(const DpJob& a, int m, int ra, int hval, int xp, int d,
                                      unsigned long long& best) {
     const int n = a.n, w = a.w;
     const int D = 2 * n - 1;
@@ -137,12 +174,169 @@ __device__ __forceinline__ void emit(const StepArgs& a, int m, int ra, int hval,
     }
 }
 
-// Walk of eq. (5) by one full wave: reduce the workgroup keys of the last
+// Common end of a step workgroup: on the image's last step its best key goes
+// to slot `slot` (its workgroup index within the image).
+__device__ __forceinline__ void finish(const DpJob& a, unsigned long long best, int slot) {
+    if (!a.key) return;
+    __shared__ unsigned long long part[kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    best = wave_max_u64(best);
+    if (lane == 0) part[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = part[0];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) m = part[q] > m ? part[q] : m;
+        a.key[slot] = m;
+    }
+}
+
+// One workgroup of a mode-0 step with the window [d - B, d + B] fixed at
+// compile time: all loads first (the window column of V_{i+1} and the H_i
+// cells), then the sliding maximum with its argmax, then the cells.
+template <int B, int DC, typename AT>
+__device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx, int by) {
+    constexpr int L = 2 * B + 1;
+    constexpr int NV = DC + 2 * B;
+    const int n = a.n, w = a.w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xp = bx * 64 + lane;
+    const int chunk = by * kWaves + wave;
+    const int d0 = -(n - 1) + chunk * DC;
+
+    int hv[DC];
+#pragma unroll
+    for (int j = 0; j < DC; ++j) hv[j] = load_h(a, xp, d0 + j);
+    int v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = load_v(a.vin, a.vin_pitch, xp, d0 - B + j, n, w);
+
+    // Suffix maxima inside window-length blocks (smallest index on ties).
+    int sv[NV], si[NV];
+#pragma unroll
+    for (int q = NV - 1; q >= 0; --q) {
+        if (q % L == L - 1 || q == NV - 1) {
+            sv[q] = v[q];
+            si[q] = q;
+        } else {
+            const bool take = v[q] >= sv[q + 1];
+            sv[q] = take ? v[q] : sv[q + 1];
+            si[q] = take ? q : si[q + 1];
+        }
+    }
+    unsigned long long best = 0;
+    int pv = 0, pi = 0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        if (q % L == 0) {
+            pv = v[q];
+            pi = q;
+        } else if (v[q] > pv) {
+            pv = v[q];
+            pi = q;
+        }
+        if (q >= 2 * B) {
+            const int j = q - 2 * B;  // window [j, q]: suffix of j's block + prefix of q's block
+            const bool s_wins = sv[j] >= pv;
+            const int m = s_wins ? sv[j] : pv;
+            const int ia = s_wins ? si[j] : pi;
+            const int ra = chunk * DC - B + ia;  // row of d' = d0 - B + ia
+            emit<AT>(a, m, ra, hv[j], xp, d0 + j, best);
+        }
+    }
+    return best;
+}
+
+// Step with the mode-0 window fixed at compile time.
+template <int B, int DC, typename AT, int CAP>
+__global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
+    const int j = dp_find_job(pk, blockIdx.x);
+    const DpJob& a = pk.job[j];
+    const int local = blockIdx.x - a.item0;
+    const int bx = local % a.items_x, by = local / a.items_x;
+    const unsigned long long best = fixed_item<B, DC, AT>(a, bx, by);
+    finish(a, best, local);
+}
+
+// Step with per-displacement windows [lo(d), hi(d)] (large mode-0 bounds, the
+// angle form, no bound at all), scanning each window.
+template <typename AT, int CAP>
+__global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
+    const int jj = dp_find_job(pk, blockIdx.x);
+    const DpJob& a = pk.job[jj];
+    const int local = blockIdx.x - a.item0;
+    const int bx = local % a.items_x, by = local / a.items_x;
+    const int n = a.n, w = a.w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xp = bx * 64 + lane;
+    const int chunk = by * kWaves + wave;
+    const int d0 = -(n - 1) + chunk * kDCGeneric;
+    const int D = 2 * n - 1;
+    unsigned long long best = 0;
+    if (a.full) {
+        // Section 2.2: every d shares the maximum of the whole successor column.
+        int m = load_v(a.vin, a.vin_pitch, xp, -(n - 1), n, w);
+        int ia = -(n - 1);
+        for (int dp = -(n - 1) + 1; dp <= n - 1; ++dp) {
+            const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
+            if (vv > m) {
+                m = vv;
+                ia = dp;
+            }
+        }
+        for (int j = 0; j < kDCGeneric; ++j)
+            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d0 + j), xp, d0 + j, best);
+    } else {
+        for (int j = 0; j < kDCGeneric; ++j) {
+            const int d = d0 + j;
+            if (d + n - 1 >= D) break;
+            int lo, hi;
+            window_of(n, a.full, a.win, a.bound, d, lo, hi);
+            int m = load_v(a.vin, a.vin_pitch, xp, lo, n, w);
+            int ia = lo;
+            for (int dp = lo + 1; dp <= hi; ++dp) {
+                const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
+                if (vv > m) {
+                    m = vv;
+                    ia = dp;
+                }
+            }
+            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d), xp, d, best);
+        }
+    }
+    finish(a, best, local);
+}
+
+// k = 1: the answer is the best masked cell of H_0 (htab).
+template <int CAP>
+__global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
+    const int jj = dp_find_job(pk, blockIdx.x);
+    const DpJob& a = pk.job[jj];
+    const int local = blockIdx.x - a.item0;
+    const int bx = local % a.items_x, by = local / a.items_x;
+    const int n = a.n, w = a.w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = bx * 64 + lane;
+    const int chunk = by * kWaves + wave;
+    const int D = 2 * n - 1;
+    unsigned long long best = 0;
+    for (int j = 0; j < kDCGeneric; ++j) {
+        const int r = chunk * kDCGeneric + j;
+        const int d = r - (n - 1);
+        if (r >= D || x >= w || x + d < 0 || x + d >= w) continue;
+        const unsigned long long kk = pack_key(a.htab[(size_t)r * a.h_pitch + x], x, r, D);
+        best = kk > best ? kk : best;
+    }
+    finish(a, best, local);
+}
+
+// Walk of eq. (5), one wave per image: reduce the workgroup keys of the last
 // step, then follow the back-pointers.  The walk is a chain of dependent
 // loads, so every load is unconditional (clamped index, result masked) and
 // the loads of one round trip are all issued before the first is used.
-template <typename AT>
-__global__ __launch_bounds__(64) void walk(StepArgs a) {
+template <typename AT, int CAP>
+__global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
+    const WalkJob& a = pk.job[blockIdx.x];
     const int lane = threadIdx.x;
     const int n = a.n, w = a.w, k = a.k;
     const int D = 2 * n - 1;
@@ -175,7 +369,7 @@ __global__ __launch_bounds__(64) void walk(StepArgs a) {
             return;
         }
         int lo, hi;
-        window_of(a, r - (n - 1), lo, hi);
+        window_of(n, a.full, a.win, a.bound, r - (n - 1), lo, hi);
         unsigned long long bestk = 0;
         for (int base = lo; base <= hi; base += 64) {
             const int dp = base + lane;
@@ -253,144 +447,6 @@ __global__ __launch_bounds__(64) void walk(StepArgs a) {
     }
 }
 
-// Common end of the last step: the workgroup's best key goes to its slot.
-__device__ __forceinline__ void finish(const StepArgs& a, unsigned long long best) {
-    if (!a.key) return;
-    __shared__ unsigned long long part[kWaves];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    best = wave_max_u64(best);
-    if (lane == 0) part[wave] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long m = part[0];
-#pragma unroll
-        for (int q = 1; q < kWaves; ++q) m = part[q] > m ? part[q] : m;
-        a.key[blockIdx.y * gridDim.x + blockIdx.x] = m;
-    }
-}
-
-// Step with the mode-0 window [d - B, d + B] fixed at compile time; each
-// thread produces DC consecutive displacements.
-template <int B, int DC, typename AT>
-__global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(StepArgs a) {
-    constexpr int L = 2 * B + 1;
-    constexpr int NV = DC + 2 * B;
-    const int n = a.n, w = a.w;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xp = blockIdx.x * 64 + lane;
-    const int chunk = blockIdx.y * kWaves + wave;
-    const int d0 = -(n - 1) + chunk * DC;
-    const bool last = a.key != nullptr;
-
-    // All loads up front: the window column of V_{i+1} and the H_i cells.
-    int v[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = load_v(a.vin, a.vin_pitch, xp, d0 - B + j, n, w);
-    int hv[DC];
-#pragma unroll
-    for (int j = 0; j < DC; ++j) hv[j] = load_h(a, xp, d0 + j);
-
-    // Suffix maxima inside window-length blocks (smallest index on ties).
-    int sv[NV], si[NV];
-#pragma unroll
-    for (int q = NV - 1; q >= 0; --q) {
-        if (q % L == L - 1 || q == NV - 1) {
-            sv[q] = v[q];
-            si[q] = q;
-        } else {
-            const bool take = v[q] >= sv[q + 1];
-            sv[q] = take ? v[q] : sv[q + 1];
-            si[q] = take ? q : si[q + 1];
-        }
-    }
-    unsigned long long best = 0;
-    int pv = 0, pi = 0;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q % L == 0) {
-            pv = v[q];
-            pi = q;
-        } else if (v[q] > pv) {
-            pv = v[q];
-            pi = q;
-        }
-        if (q >= 2 * B) {
-            const int j = q - 2 * B;  // window [j, q]: suffix of j's block + prefix of q's block
-            const bool s_wins = sv[j] >= pv;
-            const int m = s_wins ? sv[j] : pv;
-            const int ia = s_wins ? si[j] : pi;
-            const int ra = chunk * DC - B + ia;  // row of d' = d0 - B + ia
-            emit<AT>(a, m, ra, hv[j], xp, d0 + j, best);
-        }
-    }
-    (void)last;
-    finish(a, best);
-}
-
-// Step with per-displacement windows [lo(d), hi(d)] (large mode-0 bounds, the
-// angle form, no bound at all), scanning each window.
-template <typename AT>
-__global__ __launch_bounds__(64 * kWaves) void dp_step_generic(StepArgs a) {
-    const int n = a.n, w = a.w;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xp = blockIdx.x * 64 + lane;
-    const int chunk = blockIdx.y * kWaves + wave;
-    const int d0 = -(n - 1) + chunk * kDCGeneric;
-    const int D = 2 * n - 1;
-    unsigned long long best = 0;
-    if (a.full) {
-        // Section 2.2: every d shares the maximum of the whole successor column.
-        int m = load_v(a.vin, a.vin_pitch, xp, -(n - 1), n, w);
-        int ia = -(n - 1);
-        for (int dp = -(n - 1) + 1; dp <= n - 1; ++dp) {
-            const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
-            if (vv > m) {
-                m = vv;
-                ia = dp;
-            }
-        }
-        for (int j = 0; j < kDCGeneric; ++j)
-            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d0 + j), xp, d0 + j, best);
-    } else {
-        for (int j = 0; j < kDCGeneric; ++j) {
-            const int d = d0 + j;
-            if (d + n - 1 >= D) break;
-            int lo, hi;
-            window_of(a, d, lo, hi);
-            int m = load_v(a.vin, a.vin_pitch, xp, lo, n, w);
-            int ia = lo;
-            for (int dp = lo + 1; dp <= hi; ++dp) {
-                const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
-                if (vv > m) {
-                    m = vv;
-                    ia = dp;
-                }
-            }
-            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d), xp, d, best);
-        }
-    }
-    finish(a, best);
-}
-
-// k = 1: the answer is the best masked cell of H_0.
-template <typename AT>
-__global__ __launch_bounds__(64 * kWaves) void argmax_table(StepArgs a) {
-    const int n = a.n, w = a.w;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int x = blockIdx.x * 64 + lane;
-    const int chunk = blockIdx.y * kWaves + wave;
-    const int D = 2 * n - 1;
-    unsigned long long best = 0;
-    for (int j = 0; j < kDCGeneric; ++j) {
-        const int r = chunk * kDCGeneric + j;
-        const int d = r - (n - 1);
-        if (r >= D || x >= w || x + d < 0 || x + d >= w) continue;
-        const unsigned long long kk = pack_key(a.htab[(size_t)r * a.h_pitch + x], x, r, D);
-        best = kk > best ? kk : best;
-    }
-    finish(a, best);
-}
-
 // Mode-1 windows: lo(d) and hi(d) bracket every d' with n*|d'-d| <= t*(n*n + d*d').
 __global__ void angle_windows(int n, double t, int32_t* __restrict__ win) {
     const int D = 2 * n - 1;
@@ -410,24 +466,53 @@ __global__ void angle_windows(int n, double t, int32_t* __restrict__ win) {
     win[D + r] = hi;
 }
 
-template <int B, typename AT>
-void launch_fixed_b(int dc, dim3 grid, hipStream_t s, const StepArgs& a) {
-    if (dc == 8)
-        hipLaunchKernelGGL((dp_step_fixed<B, 8, AT>), grid, dim3(64 * kWaves), 0, s, a);
-    else
-        hipLaunchKernelGGL((dp_step_fixed<B, 16, AT>), grid, dim3(64 * kWaves), 0, s, a);
+// ---- host side ---------------------------------------------------------------
+
+// Kernels of one step launch are chosen by this class; images of one class
+// can share launches.
+struct DpClass {
+    int kind;   // WindowKind
+    int bound;  // fixed kernels: the template bound
+    int dc;     // fixed kernels: displacements per thread
+    bool a16;
+    bool operator==(const DpClass& o) const {
+        return kind == o.kind && bound == o.bound && dc == o.dc && a16 == o.a16;
+    }
+};
+
+DpClass class_of(const DpJobSpec& j) {
+    DpClass c;
+    c.kind = (int)j.plan.kind;
+    const bool fixed = j.plan.kind == WindowKind::Fixed;
+    c.bound = fixed ? j.plan.bound : 0;
+    c.dc = fixed ? j.plan.dc : kDCGeneric;
+    c.a16 = j.plan.a16;
+    if (!fixed) c.kind = (int)WindowKind::Generic;  // one scanning kernel for every other kind
+    return c;
 }
 
-template <typename AT>
-hipError_t launch_step(const DpPlan& plan, dim3 grid_fixed, dim3 grid_generic, hipStream_t s,
-                       const StepArgs& a) {
-    if (plan.kind != WindowKind::Fixed) {
-        hipLaunchKernelGGL((dp_step_generic<AT>), grid_generic, dim3(64 * kWaves), 0, s, a);
+int items_y_of(const Geometry& g, int dc) {
+    const int chunks = (g.D + dc - 1) / dc;
+    return (chunks + kWaves - 1) / kWaves;
+}
+
+template <int B, typename AT, int CAP>
+void launch_fixed_b(int dc, hipStream_t s, const DpPack<CAP>& pk) {
+    if (dc == 8)
+        hipLaunchKernelGGL((dp_step_fixed<B, 8, AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
+    else
+        hipLaunchKernelGGL((dp_step_fixed<B, 16, AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
+}
+
+template <typename AT, int CAP>
+hipError_t launch_step(const DpClass& c, hipStream_t s, const DpPack<CAP>& pk) {
+    if (c.kind != (int)WindowKind::Fixed) {
+        hipLaunchKernelGGL((dp_step_generic<AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
         return hipSuccess;
     }
 #define FHTP_B(BB) \
-    case BB: launch_fixed_b<BB, AT>(plan.dc, grid_fixed, s, a); return hipSuccess;
-    switch (plan.bound) {
+    case BB: launch_fixed_b<BB, AT, CAP>(c.dc, s, pk); return hipSuccess;
+    switch (c.bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
         FHTP_B(9) FHTP_B(10) FHTP_B(11) FHTP_B(12) FHTP_B(13) FHTP_B(14) FHTP_B(15) FHTP_B(16)
         default: return hipErrorInvalidValue;
@@ -435,63 +520,142 @@ hipError_t launch_step(const DpPlan& plan, dim3 grid_fixed, dim3 grid_generic, h
 #undef FHTP_B
 }
 
-template <typename AT>
-hipError_t launch_dp_t(const int32_t* tables, const Geometry& g, const DpPlan& plan,
-                       const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t s) {
-    const int n = g.n, w = g.w, k = g.k, D = g.D;
-    const size_t band_stride = (size_t)D * g.W;
-    const int chunks16 = (D + 15) / 16;
-    const int chunks_fixed = (D + plan.dc - 1) / plan.dc;
-    const dim3 grid_fixed((w + 63) / 64, (chunks_fixed + kWaves - 1) / kWaves, 1);
-    const dim3 grid_generic((w + 63) / 64, (chunks16 + kWaves - 1) / kWaves, 1);
-    AT* A = static_cast<AT*>(buf.a);
-    const size_t a_plane = (size_t)D * g.pitch;
-
-    StepArgs a{};
-    a.n = n;
-    a.w = w;
-    a.bound = plan.bound;
-    a.full = plan.kind == WindowKind::Full;
-    a.win = plan.kind == WindowKind::Angle ? buf.win : nullptr;
-    a.a_base = A;
-    a.a_plane = a_plane;
-    a.a_pitch = g.pitch;
-    a.k = k;
-    a.score = score;
-    a.xs = xs;
-    a.v_pitch = g.pitch;
+// Common fields of an image's step descriptor.
+DpJob base_job(const DpJobSpec& J) {
+    const Geometry& g = J.g;
+    DpJob a{};
+    a.n = g.n;
+    a.w = g.w;
+    a.bound = J.plan.bound;
+    a.full = J.plan.kind == WindowKind::Full;
+    a.win = J.plan.kind == WindowKind::Angle ? J.buf.win : nullptr;
     a.h_pitch = g.W;
+    a.v_pitch = g.pitch;
+    a.a_pitch = g.pitch;
+    a.items_x = (g.w + 63) / 64;
+    return a;
+}
 
-    if (plan.kind == WindowKind::Angle)
-        hipLaunchKernelGGL(angle_windows, dim3((D + 255) / 256), dim3(256), 0, s, n,
-                           plan.tan_gamma, buf.win);
-    a.key = buf.key;
-    if (k == 1) {
-        a.htab = tables;
-        a.n_keys = (int)(grid_generic.x * grid_generic.y);
-        hipLaunchKernelGGL((argmax_table<AT>), grid_generic, dim3(64 * kWaves), 0, s, a);
-    } else {
-        a.vin = tables + (size_t)(k - 1) * band_stride;
-        a.vin_pitch = g.W;
-        for (int i = k - 2; i >= 0; --i) {
+// Steps of a pack of images of one class (each with k >= 2).
+template <typename AT, int CAP>
+hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
+    int max_steps = 0;
+    for (const DpJobSpec* J : jobs) max_steps = std::max(max_steps, J->g.k - 1);
+    for (int st = 0; st < max_steps; ++st) {
+        DpPack<CAP> pk{};
+        long long total = 0;
+        int cnt = 0;
+        for (const DpJobSpec* J : jobs) {
+            const Geometry& g = J->g;
+            if (g.k - 1 <= st) continue;
+            const int i = g.k - 2 - st;  // band of this step
+            const size_t band = (size_t)g.D * g.W;
+            const size_t plane = (size_t)g.D * g.pitch;
+            DpJob a = base_job(*J);
+            a.vin = st == 0 ? J->tables + (size_t)(g.k - 1) * band
+                            : J->buf.vplanes + (size_t)((i + 1) & 1) * plane;
+            a.vin_pitch = st == 0 ? g.W : g.pitch;
+            a.htab = J->tables + (size_t)i * band;
             const bool last = i == 0;
-            a.htab = tables + (size_t)i * band_stride;
-            a.vout = last ? nullptr : buf.v[i & 1];
-            a.aout = last ? nullptr : A + (size_t)(i - 1) * a_plane;
-            a.key = last ? buf.key : nullptr;
-            const dim3 grid = plan.kind == WindowKind::Fixed ? grid_fixed : grid_generic;
-            a.n_keys = (int)(grid.x * grid.y);
-            hipError_t e = launch_step<AT>(plan, grid_fixed, grid_generic, s, a);
-            if (e != hipSuccess) return e;
-            if (!last) {
-                a.vin = a.vout;
-                a.vin_pitch = g.pitch;
-            }
+            // two planes in turn: step i only overwrites V_{i+2}, whose readers
+            // (step i+1) finished with the previous launch
+            a.vout = last ? nullptr : J->buf.vplanes + (size_t)(i & 1) * plane;
+            a.aout = last ? nullptr : static_cast<AT*>(J->buf.a) + (size_t)(i - 1) * plane;
+            a.key = last ? J->buf.key : nullptr;
+            a.item0 = (int)total;
+            total += (long long)a.items_x * items_y_of(g, c.dc);
+            if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            pk.job[cnt++] = a;
         }
-        a.key = buf.key;
+        pk.count = cnt;
+        pk.total = (int)total;
+        hipError_t e = launch_step<AT, CAP>(c, s, pk);
+        if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((walk<AT>), dim3(1), dim3(64), 0, s, a);
-    return hipGetLastError();
+    return hipSuccess;
+}
+
+template <typename AT, int CAP>
+hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
+    for (size_t q0 = 0; q0 < jobs.size(); q0 += CAP) {
+        WalkPack<CAP> pk{};
+        const int cnt = (int)std::min<size_t>(CAP, jobs.size() - q0);
+        for (int q = 0; q < cnt; ++q) {
+            const DpJobSpec& J = *jobs[q0 + q];
+            const Geometry& g = J.g;
+            const DpClass c = class_of(J);
+            WalkJob& a = pk.job[q];
+            a.key = J.buf.key;
+            a.n_keys = g.k == 1 ? (int)(((g.w + 63) / 64) * items_y_of(g, kDCGeneric))
+                                : (int)(((g.w + 63) / 64) * items_y_of(g, c.dc));
+            a.vin = g.k == 2 ? J.tables + (size_t)g.D * g.W : J.buf.vplanes + (size_t)g.D * g.pitch;
+            a.vin_pitch = g.k == 2 ? g.W : g.pitch;
+            a.a_base = J.buf.a;
+            a.a_plane = (size_t)g.D * g.pitch;
+            a.a_pitch = g.pitch;
+            a.n = g.n;
+            a.w = g.w;
+            a.k = g.k;
+            a.bound = J.plan.bound;
+            a.full = J.plan.kind == WindowKind::Full;
+            a.win = J.plan.kind == WindowKind::Angle ? J.buf.win : nullptr;
+            a.score = J.score;
+            a.xs = J.xs;
+        }
+        pk.count = cnt;
+        hipLaunchKernelGGL((walk<AT, CAP>), dim3(cnt), dim3(64), 0, s, pk);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename AT, int CAP>
+hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
+    // k = 1: the argmax of H_0, in packs.
+    std::vector<const DpJobSpec*> single;
+    for (const DpJobSpec* J : jobs)
+        if (J->g.k == 1) single.push_back(J);
+    for (size_t q0 = 0; q0 < single.size(); q0 += CAP) {
+        DpPack<CAP> pk{};
+        long long total = 0;
+        const int cnt = (int)std::min<size_t>(CAP, single.size() - q0);
+        for (int q = 0; q < cnt; ++q) {
+            const DpJobSpec& J = *single[q0 + q];
+            DpJob a = base_job(J);
+            a.htab = J.tables;
+            a.key = J.buf.key;
+            a.item0 = (int)total;
+            total += (long long)a.items_x * items_y_of(J.g, kDCGeneric);
+            if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            pk.job[q] = a;
+        }
+        pk.count = cnt;
+        pk.total = (int)total;
+        hipLaunchKernelGGL((argmax_table<CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
+    }
+    // k >= 2: step launches per class, in packs.
+    std::vector<const DpJobSpec*> rest;
+    for (const DpJobSpec* J : jobs)
+        if (J->g.k >= 2) rest.push_back(J);
+    std::vector<bool> done(rest.size(), false);
+    for (size_t q = 0; q < rest.size(); ++q) {
+        if (done[q]) continue;
+        const DpClass c = class_of(*rest[q]);
+        std::vector<const DpJobSpec*> group;
+        for (size_t r = q; r < rest.size(); ++r)
+            if (!done[r] && class_of(*rest[r]) == c) {
+                group.push_back(rest[r]);
+                done[r] = true;
+            }
+        for (size_t q0 = 0; q0 < group.size(); q0 += CAP) {
+            std::vector<const DpJobSpec*> pack(group.begin() + q0,
+                                               group.begin() + std::min(group.size(), q0 + CAP));
+            hipError_t e = run_steps<AT, CAP>(c, pack, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return run_walks<AT, CAP>(jobs, s);
 }
 
 }  // namespace
@@ -500,8 +664,7 @@ size_t dp_plane_bytes(const Geometry& g) { return (size_t)g.D * g.pitch * sizeof
 
 size_t dp_key_count(const Geometry& g) {
     // workgroups of the last step at 8 displacements per thread (the largest grid)
-    const size_t chunks = (size_t)(g.D + 7) / 8;
-    return (size_t)((g.w + 63) / 64) * ((chunks + kWaves - 1) / kWaves);
+    return (size_t)((g.w + 63) / 64) * items_y_of(g, 8);
 }
 
 size_t dp_backptr_bytes(const Geometry& g, bool a16) {
@@ -510,13 +673,33 @@ size_t dp_backptr_bytes(const Geometry& g, bool a16) {
     return planes * g.D * g.pitch * (a16 ? 2 : 1);
 }
 
+hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t s) {
+    std::vector<const DpJobSpec*> a8, a16;
+    for (int q = 0; q < count; ++q) {
+        const DpJobSpec& J = jobs[q];
+        if (J.plan.kind == WindowKind::Fixed &&
+            (J.plan.bound < 0 || J.plan.bound > kMaxFixedB || (J.plan.dc != 8 && J.plan.dc != 16)))
+            return hipErrorInvalidValue;
+        if (J.plan.kind == WindowKind::Angle)
+            hipLaunchKernelGGL(angle_windows, dim3((J.g.D + 255) / 256), dim3(256), 0, s, J.g.n,
+                               J.plan.tan_gamma, J.buf.win);
+        (J.plan.a16 ? a16 : a8).push_back(&J);
+    }
+    hipError_t e = hipSuccess;
+    if (count == 1) {
+        e = a8.empty() ? launch_dp_jobs_t<uint16_t, 1>(a16, s) : launch_dp_jobs_t<uint8_t, 1>(a8, s);
+    } else {
+        if (!a8.empty()) e = launch_dp_jobs_t<uint8_t, kPack>(a8, s);
+        if (e == hipSuccess && !a16.empty()) e = launch_dp_jobs_t<uint16_t, kPack>(a16, s);
+    }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
                      const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream) {
-    if (plan.kind == WindowKind::Fixed &&
-        (plan.bound < 0 || plan.bound > kMaxFixedB || (plan.dc != 8 && plan.dc != 16)))
-        return hipErrorInvalidValue;
-    if (plan.a16) return launch_dp_t<uint16_t>(tables, g, plan, buf, score, xs, stream);
-    return launch_dp_t<uint8_t>(tables, g, plan, buf, score, xs, stream);
+    DpJobSpec j{tables, g, plan, buf, score, xs};
+    return launch_dp_jobs(&j, 1, stream);
 }
 
 }  // namespace fhtp

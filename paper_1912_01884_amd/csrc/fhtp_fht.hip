@@ -21,6 +21,9 @@
 // stores are coalesced along x.  Bands taller than 2^7 rows run the same kernel
 // on 128-row sub-blocks, then a second kernel adds the sub-blocks along the
 // coarse levels of the recursion.
+#include <algorithm>
+#include <vector>
+
 #include "fhtp_internal.h"
 
 namespace fhtp {
@@ -35,22 +38,84 @@ __device__ __forceinline__ int dyadic_offset(int p, int s, int y) {
     return off;
 }
 
+// Buffer resource over [base, base + bytes): loads beyond the extent read 0
+// and stores beyond it are dropped by the hardware.  The third descriptor
+// word selects 32-bit raw (untyped) access on the gfx9 family.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <typename PixT>
+__device__ __forceinline__ uint32_t buffer_pixel(__amdgpu_buffer_rsrc_t r, unsigned int voff,
+                                                 unsigned int soff) {
+    if constexpr (sizeof(PixT) == 1)
+        return __builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+
 template <int P>
 struct RegCfg {
     static constexpr int N = 1 << P;
     static constexpr int NT = (P >= 7) ? 512 : 256;
-    static constexpr int T = NT - (N - 1);             // columns produced per workgroup
     static constexpr int HALF = (N >= 2) ? N / 2 : 1;
     static constexpr int LW = NT + HALF;               // LDS row width (halo reads stay inside)
     static constexpr int LDS_WORDS = (N >= 2) ? (N / 2) * LW : 1;
+    static constexpr int NPK = (N + 1) / 2;            // packed 16-bit pixel pairs per column
+    static constexpr int NDIR = (P == 0) ? 1 : 2;      // one-row bands have only d = 0
+    // Fetch the next item's pixels during the current item's stages.  At
+    // n = 128 the 128 running sums leave no registers for it.
+    static constexpr bool PREFETCH = P <= 6;
 };
 
-// One stage of the recursion on the column held in v.
+// One stage of the recursion on the column held in v, in place: the operands
+// of the lower half-blocks go through LDS, and outputs (2t, 2t+1) overwrite
+// slots that no later t of the same stage still reads (t runs downwards).
 template <int N, int J, int LW>
 __device__ __forceinline__ void fht_stage(int32_t (&v)[N], int32_t* lds, int tid) {
     constexpr int half = 1 << (J - 1);
     constexpr int blocks = N >> J;
+    // The lane's LDS byte address, made opaque to the optimiser so that per-row
+    // addresses are formed next to their use instead of being hoisted out of
+    // the loop into one register per row.
+    unsigned int lane_addr = (unsigned int)tid * 4u;
     __syncthreads();  // the previous stage's LDS reads are complete
+#pragma unroll
+    for (int b = 0; b < blocks; ++b)
+#pragma unroll
+        for (int t = 0; t < half; ++t) lds[(b * half + t) * LW + tid] = v[b * 2 * half + half + t];
+    __syncthreads();
+    // Groups of at most 16 operand pairs, with scheduling barriers between
+    // them, so the compiler cannot hoist every LDS read of the stage at once
+    // (that would need 2n live registers).
+    constexpr int G = half < 16 ? half : 16;
+#pragma unroll
+    for (int b = 0; b < blocks; ++b) {
+#pragma unroll
+        for (int g = half / G - 1; g >= 0; --g) {
+            asm volatile("" : "+v"(lane_addr));
+            const char* lbase = reinterpret_cast<const char*>(lds) + lane_addr;
+#pragma unroll
+            for (int t = g * G + G - 1; t >= g * G; --t) {
+                const int32_t a = v[b * 2 * half + t];
+                const int32_t* row =
+                    reinterpret_cast<const int32_t*>(lbase + ((b * half + t) * LW + t) * 4);
+                v[b * 2 * half + 2 * t + 1] = a + row[1];
+                v[b * 2 * half + 2 * t] = a + row[0];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The same stage with no scheduling constraints: the compiler may issue all
+// LDS reads of the stage together (more registers, more memory parallelism).
+template <int N, int J, int LW>
+__device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, int tid) {
+    constexpr int half = 1 << (J - 1);
+    constexpr int blocks = N >> J;
+    __syncthreads();
 #pragma unroll
     for (int b = 0; b < blocks; ++b)
 #pragma unroll
@@ -71,136 +136,332 @@ __device__ __forceinline__ void fht_stage(int32_t (&v)[N], int32_t* lds, int tid
     for (int q = 0; q < N; ++q) v[q] = nv[q];
 }
 
-template <int N, int J, int P, int LW>
+template <int N, int J, int P, int LW, bool GROUPED>
 __device__ __forceinline__ void fht_stages(int32_t (&v)[N], int32_t* lds, int tid) {
     if constexpr (J <= P) {
-        fht_stage<N, J, LW>(v, lds, tid);
-        fht_stages<N, J + 1, P, LW>(v, lds, tid);
+        if constexpr (GROUPED)
+            fht_stage<N, J, LW>(v, lds, tid);
+        else
+            fht_stage_free<N, J, LW>(v, lds, tid);
+        fht_stages<N, J + 1, P, LW, GROUPED>(v, lds, tid);
     }
 }
 
-// Grid: x = block * tiles + tile over row blocks of 2^P rows, y = direction
-// (0 right-leaning, 1 left-leaning).  Output modes:
-//   to_table: tables[blk][n-1 +- s][x] of a band of n = 2^P rows (d = 0 only from y = 0);
+// One run of the register kernel for one image: its row blocks of 2^P rows,
+// both directions, split into column tiles.  A launch takes a pack of runs
+// (several images of the same band height) and numbers their work items
+// consecutively from item0.
+struct FhtJob {
+    const void* img;  // first row of row block 0
+    int32_t* out;     // tables [blocks][2n-1][W], or sub-block scratch
+    int w, W;         // image width, table width (w + band height)
+    int T, tiles;     // columns produced per tile, tiles per row block
+    int item0;        // first work item of this run in the launch
+    int to_table;     // 1: band tables; 0: c-space sub-block scratch
+};
+
+constexpr int kPack = 32;  // runs per launch (kernel-argument size)
+
+// CAP runs per launch: 1 for a single image (small kernel arguments), kPack for batches.
+template <int CAP>
+struct FhtPack {
+    FhtJob job[CAP];
+    int count;  // runs in this pack
+    int total;  // work items in this launch
+};
+
+// The run a work item belongs to (uniform across the workgroup).
+template <int CAP>
+__device__ __forceinline__ int fht_find_job(const FhtPack<CAP>& pk, int item) {
+    int j = 0;
+    if constexpr (CAP > 1)
+        for (int q = 1; q < pk.count; ++q) j = item >= pk.job[q].item0 ? q : j;
+    return j;
+}
+
+struct FhtItem {
+    int blk, dir, c, ximg;
+    bool inside;
+};
+
+template <int NDIR>
+__device__ __forceinline__ FhtItem fht_decode(const FhtJob& J, int local, int tid) {
+    FhtItem it;
+    const int tile = local % J.tiles;
+    const int bd = local / J.tiles;  // blk * NDIR + dir
+    it.blk = bd / NDIR;
+    it.dir = bd % NDIR;
+    it.c = tile * J.T + tid;
+    const int cm = it.c % J.W;
+    it.ximg = it.dir == 0 ? cm : (J.W - 1 - cm);
+    it.inside = it.ximg < J.w;
+    return it;
+}
+
+// Pixels of one c-space column, two rows per 32-bit register.  The row block
+// base is uniform (scalar registers), rows are scalar offsets, and the column
+// is one 32-bit lane offset shared by every row.
+template <int N, int NPK, int NDIR, typename PixT>
+__device__ __forceinline__ void fetch_column(const FhtJob& J, int local, int tid,
+                                             uint32_t (&pk)[NPK]) {
+    const FhtItem it = fht_decode<NDIR>(J, local, tid);
+    const PixT* img = static_cast<const PixT*>(J.img);
+    const unsigned int row_bytes = (unsigned int)J.w * sizeof(PixT);
+    const __amdgpu_buffer_rsrc_t r =
+        make_rsrc(img + (size_t)it.blk * N * (size_t)J.w, (unsigned int)N * row_bytes);
+    const unsigned int voff = (it.inside ? (unsigned int)it.ximg : 0u) * sizeof(PixT);
+#pragma unroll
+    for (int q = 0; q < NPK; ++q) {
+        const uint32_t lo = buffer_pixel<PixT>(r, voff, (unsigned int)(2 * q) * row_bytes);
+        uint32_t hi = 0u;
+        if constexpr (N > 1) hi = buffer_pixel<PixT>(r, voff, (unsigned int)(2 * q + 1) * row_bytes);
+        pk[q] = it.inside ? (lo | (hi << 16)) : 0u;
+    }
+}
+
+// Same pixels straight into the running-sum registers (no prefetch).
+template <int N, int NDIR, typename PixT>
+__device__ __forceinline__ void fetch_column_direct(const FhtJob& J, int local, int tid,
+                                                    int32_t (&v)[N]) {
+    const FhtItem it = fht_decode<NDIR>(J, local, tid);
+    const PixT* img = static_cast<const PixT*>(J.img);
+    const unsigned int row_bytes = (unsigned int)J.w * sizeof(PixT);
+    const __amdgpu_buffer_rsrc_t r =
+        make_rsrc(img + (size_t)it.blk * N * (size_t)J.w, (unsigned int)N * row_bytes);
+    // Lanes past the image read beyond the buffer extent, which returns 0.
+    const unsigned int voff = it.inside ? (unsigned int)it.ximg * sizeof(PixT) : 0x80000000u;
+#pragma unroll
+    for (int y = 0; y < N; ++y) v[y] = (int32_t)buffer_pixel<PixT>(r, voff, (unsigned int)y * row_bytes);
+}
+
+// Output modes of a run:
+//   to_table: tables[blk][n-1 +- s][x] of a band of n = 2^P rows (d = 0 only from dir 0);
 //   else:     scratch[(blk*2 + dir)*2^P + s][c] in c-space (pass 1 of tall bands).
-template <int P, typename PixT>
-__global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(const PixT* __restrict__ img,
-                                                                int w, int W, int tiles,
-                                                                int32_t* __restrict__ out,
-                                                                int to_table) {
+template <int P>
+__device__ __forceinline__ void fht_store(const FhtJob& J, int local, int tid,
+                                          const int32_t (&v)[1 << P]) {
+    using C = RegCfg<P>;
+    constexpr int N = C::N;
+    const FhtItem it = fht_decode<C::NDIR>(J, local, tid);
+    const int W = J.W;
+    if (tid >= J.T || it.c >= W) return;
+    const unsigned int row_bytes = (unsigned int)W * 4u;
+    if (J.to_table) {
+        constexpr int D = 2 * N - 1;
+        const unsigned int voff = (unsigned int)(it.dir == 0 ? it.c : (W - 1 - it.c)) * 4u;
+        const __amdgpu_buffer_rsrc_t r =
+            make_rsrc(J.out + (size_t)it.blk * D * (size_t)W, (unsigned int)D * row_bytes);
+        if (it.dir == 0) {
+#pragma unroll
+            for (int s = 0; s < N; ++s)
+                __builtin_amdgcn_raw_buffer_store_b32(
+                    v[s], r, (int)voff, (int)((unsigned int)(N - 1 + s) * row_bytes), 0);
+        } else {
+#pragma unroll
+            for (int s = 1; s < N; ++s)
+                __builtin_amdgcn_raw_buffer_store_b32(
+                    v[s], r, (int)voff, (int)((unsigned int)(N - 1 - s) * row_bytes), 0);
+        }
+    } else {
+        const __amdgpu_buffer_rsrc_t r =
+            make_rsrc(J.out + (size_t)(it.blk * C::NDIR + it.dir) * N * (size_t)W,
+                      (unsigned int)N * row_bytes);
+        const unsigned int voff = (unsigned int)it.c * 4u;
+#pragma unroll
+        for (int s = 0; s < N; ++s)
+            __builtin_amdgcn_raw_buffer_store_b32(v[s], r, (int)voff,
+                                                  (int)((unsigned int)s * row_bytes), 0);
+    }
+}
+
+// Work item = (run, row block, direction, column tile).  Prefetching variants
+// loop over items with a stride of the grid, fetching the next item's pixels
+// while the current one runs its stages; the others take one item per
+// workgroup.  A tile produces T columns (T <= NT - (n-1)); the rest of its NT
+// columns are halo.
+template <int P, typename PixT, int CAP>
+__global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk) {
     using C = RegCfg<P>;
     constexpr int N = C::N;
     __shared__ int32_t lds[C::LDS_WORDS];
-
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x % tiles;
-    const int blk = blockIdx.x / tiles;
-    const int dir = blockIdx.y;
-    const int c = tile * C::T + tid;
-    const int cm = c % W;
-    const int ximg = dir == 0 ? cm : (W - 1 - cm);
+    const int total = pk.total;
 
-    int32_t v[N];
-    const PixT* src = img + (size_t)blk * N * (size_t)w;
-    const bool inside = ximg < w;
+    uint32_t pre[C::NPK];
+    int item = blockIdx.x;
+    if constexpr (C::PREFETCH) {
+        const int j = fht_find_job(pk, item);
+        fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[j], item - pk.job[j].item0, tid, pre);
+    }
+    while (item < total) {
+        const int j = fht_find_job(pk, item);
+        const FhtJob& J = pk.job[j];
+        const int local = item - J.item0;
+        int32_t v[N];
+        if constexpr (C::PREFETCH) {
 #pragma unroll
-    for (int y = 0; y < N; ++y) v[y] = inside ? (int32_t)src[(size_t)y * w + ximg] : 0;
-
-    fht_stages<N, 1, P, C::LW>(v, lds, tid);
-
-    if (tid >= C::T || c >= W) return;
-    if (to_table) {
-        constexpr int D = 2 * N - 1;
-        const int xo = dir == 0 ? c : (W - 1 - c);
-        int32_t* base = out + (size_t)blk * D * (size_t)W + xo;
-#pragma unroll
-        for (int s = 0; s < N; ++s) {
-            if (dir == 0) {
-                base[(size_t)(N - 1 + s) * W] = v[s];
-            } else if (s > 0) {
-                base[(size_t)(N - 1 - s) * W] = v[s];
+            for (int q = 0; q < C::NPK; ++q) {
+                v[2 * q] = (int32_t)(pre[q] & 0xffffu);
+                if (2 * q + 1 < N) v[2 * q + 1] = (int32_t)(pre[q] >> 16);
             }
+        } else {
+            fetch_column_direct<N, C::NDIR, PixT>(J, local, tid, v);
         }
-    } else {
-        int32_t* base = out + (size_t)(blk * 2 + dir) * N * (size_t)W + c;
-#pragma unroll
-        for (int s = 0; s < N; ++s) base[(size_t)s * W] = v[s];
+        const int next = item + (int)gridDim.x;
+        if constexpr (C::PREFETCH) {
+            // Unconditional prefetch (the last round re-reads its own item).
+            const int nx = next < total ? next : item;
+            const int jn = fht_find_job(pk, nx);
+            fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[jn], nx - pk.job[jn].item0, tid, pre);
+        }
+
+        fht_stages<N, 1, P, C::LW, C::PREFETCH>(v, lds, tid);
+        fht_store<P>(J, local, tid, v);
+        item = next;
     }
 }
 
 // Pass 2 for bands of n = 2^p > 2^7 rows: the band is M = n/128 sub-blocks whose
 // FHTs (fine shift sf = s >> (p-7)) sit in `sub`; the line of shift s starts in
 // sub-block m at c + D_s(m*128), so T(c, s) = sum_m sub[m][sf][(c + D_s(128 m)) mod W].
-__global__ __launch_bounds__(256) void fht_combine_kernel(const int32_t* __restrict__ sub,
-                                                          int p, int W, int tiles_x,
-                                                          int32_t* __restrict__ tables) {
+// A workgroup covers 256 columns of one (band, direction) for kShiftGroup
+// consecutive shifts; the offsets D_s(128 m) are uniform (scalar) per shift.
+struct CombineJob {
+    const int32_t* sub;
+    int32_t* tables;
+    int p, W, k, tiles_x;
+    int item0;
+};
+
+struct CombinePack {
+    CombineJob job[kPack];
+    int count;
+    int total;
+};
+
+constexpr int kShiftGroup = 16;
+
+template <int SH>  // SH = p - 7, M = 2^SH sub-blocks per band
+__global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
+    constexpr int M = 1 << SH;
+    const int item = blockIdx.x;
+    int j = 0;
+    for (int q = 1; q < pk.count; ++q) j = item >= pk.job[q].item0 ? q : j;
+    const CombineJob& J = pk.job[j];
+    const int p = J.p;
     const int n = 1 << p;
     const int D = 2 * n - 1;
-    const int M = n >> kRegMaxP;
-    const int sh = p - kRegMaxP;
-    const int tile = blockIdx.x % tiles_x;
-    const int s = blockIdx.x / tiles_x;
-    const int dir = blockIdx.y;
-    const int band = blockIdx.z;
+    const int W = J.W;
+    const int groups = n / kShiftGroup;
+    int local = item - J.item0;  // ((band * 2 + dir) * groups + g) * tiles_x + tile
+    const int tile = local % J.tiles_x;
+    local /= J.tiles_x;
+    const int g = local % groups;
+    const int bd = local / groups;
+    const int dir = bd & 1;
+    const int band = bd >> 1;
     const int c = tile * 256 + threadIdx.x;
-    if (c >= W || (dir == 1 && s == 0)) return;
-    const int sf = s >> sh;
-    int32_t acc = 0;
-    for (int m = 0; m < M; ++m) {
-        int cc = c + dyadic_offset(p, s, m << kRegMaxP);
-        cc %= W;
-        acc += sub[((size_t)((band * M + m) * 2 + dir) * (1 << kRegMaxP) + sf) * W + cc];
-    }
+    if (c >= W) return;
+    const size_t row = (size_t)W;
+    const int32_t* base = J.sub + (size_t)band * M * 2 * (1 << kRegMaxP) * row;
+    int32_t* out = J.tables + (size_t)band * D * row;
     const int xo = dir == 0 ? c : (W - 1 - c);
-    const int r = dir == 0 ? (n - 1 + s) : (n - 1 - s);
-    tables[((size_t)band * D + r) * W + xo] = acc;
+    for (int t = 0; t < kShiftGroup; ++t) {
+        const int s = g * kShiftGroup + t;
+        if (dir == 1 && s == 0) continue;
+        const int sf = s >> SH;
+        int32_t acc = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            int cc = c + dyadic_offset(p, s, m << kRegMaxP);
+            cc -= cc >= W ? W : 0;  // offsets are below n < W, so one wrap at most
+            acc += base[((size_t)(m * 2 + dir) * (1 << kRegMaxP) + sf) * row + cc];
+        }
+        const int r = dir == 0 ? (n - 1 + s) : (n - 1 - s);
+        out[(size_t)r * row + xo] = acc;
+    }
 }
 
-template <int P, typename PixT>
-hipError_t launch_reg(const PixT* img, int w, int W, int blocks, int32_t* out, int to_table,
-                      hipStream_t stream) {
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// One register-kernel run to schedule (host side).
+struct RegRun {
+    const void* img;
+    int dtype, p;   // pixel type, log2 of the row-block height the kernel runs
+    int w, W, blocks, to_table;
+    int32_t* out;
+};
+
+template <int P, typename PixT, int CAP>
+hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
     using C = RegCfg<P>;
-    const int tiles = (W + C::T - 1) / C::T;
-    const long long gx = (long long)tiles * blocks;
-    if (gx > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    dim3 grid((unsigned)gx, (P == 0) ? 1 : 2, 1);
-    hipLaunchKernelGGL((fht_reg_kernel<P, PixT>), grid, dim3(C::NT), 0, stream, img, w, W, tiles,
-                       out, to_table);
+    static int occupancy = 0;  // resident workgroups per CU for this instantiation
+    if (occupancy == 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fht_reg_kernel<P, PixT, CAP>, C::NT,
+                                                         0) != hipSuccess ||
+            occ <= 0)
+            occ = 1;
+        occupancy = occ;
+    }
+    const int Tmax = C::NT - (C::N - 1);
+    FhtPack<CAP> pk{};
+    long long total = 0;
+    for (int q = 0; q < count; ++q) {
+        const RegRun& r = runs[q];
+        // Tile width: the fewest tiles per row block of at most Tmax columns,
+        // spread evenly so every tile does about the same work.
+        const int tiles = (r.W + Tmax - 1) / Tmax;
+        FhtJob& J = pk.job[q];
+        J.img = r.img;
+        J.out = r.out;
+        J.w = r.w;
+        J.W = r.W;
+        J.tiles = tiles;
+        J.T = (r.W + tiles - 1) / tiles;
+        J.item0 = (int)total;
+        J.to_table = r.to_table;
+        total += (long long)tiles * r.blocks * C::NDIR;
+        if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    }
+    pk.count = count;
+    pk.total = (int)total;
+    if (total == 0) return hipSuccess;
+    const long long slots = C::PREFETCH ? (long long)occupancy * device_cus() : total;
+    const int grid = (int)(total < slots ? total : slots);
+    hipLaunchKernelGGL((fht_reg_kernel<P, PixT, CAP>), dim3(grid), dim3(C::NT), 0, stream, pk);
     return hipGetLastError();
 }
 
-template <typename PixT>
-hipError_t launch_reg_p(int p, const PixT* img, int w, int W, int blocks, int32_t* out,
-                        int to_table, hipStream_t stream) {
+template <typename PixT, int CAP>
+hipError_t launch_reg_p(int p, const RegRun* runs, int count, hipStream_t stream) {
     switch (p) {
-        case 0: return launch_reg<0>(img, w, W, blocks, out, to_table, stream);
-        case 1: return launch_reg<1>(img, w, W, blocks, out, to_table, stream);
-        case 2: return launch_reg<2>(img, w, W, blocks, out, to_table, stream);
-        case 3: return launch_reg<3>(img, w, W, blocks, out, to_table, stream);
-        case 4: return launch_reg<4>(img, w, W, blocks, out, to_table, stream);
-        case 5: return launch_reg<5>(img, w, W, blocks, out, to_table, stream);
-        case 6: return launch_reg<6>(img, w, W, blocks, out, to_table, stream);
-        case 7: return launch_reg<7>(img, w, W, blocks, out, to_table, stream);
+        case 0: return launch_reg_pack<0, PixT, CAP>(runs, count, stream);
+        case 1: return launch_reg_pack<1, PixT, CAP>(runs, count, stream);
+        case 2: return launch_reg_pack<2, PixT, CAP>(runs, count, stream);
+        case 3: return launch_reg_pack<3, PixT, CAP>(runs, count, stream);
+        case 4: return launch_reg_pack<4, PixT, CAP>(runs, count, stream);
+        case 5: return launch_reg_pack<5, PixT, CAP>(runs, count, stream);
+        case 6: return launch_reg_pack<6, PixT, CAP>(runs, count, stream);
+        case 7: return launch_reg_pack<7, PixT, CAP>(runs, count, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename PixT>
-hipError_t launch_fht_t(const PixT* img, const Geometry& g, int32_t* tables, void* scratch,
-                        hipStream_t stream) {
-    if (g.p <= kRegMaxP) return launch_reg_p<PixT>(g.p, img, g.w, g.W, g.k, tables, 1, stream);
-    // Tall bands: 128-row sub-blocks first, then the coarse levels.
-    const int sub_blocks = g.h >> kRegMaxP;
-    int32_t* sub = static_cast<int32_t*>(scratch);
-    hipError_t e = launch_reg_p<PixT>(kRegMaxP, img, g.w, g.W, sub_blocks, sub, 0, stream);
-    if (e != hipSuccess) return e;
-    const int tiles_x = (g.W + 255) / 256;
-    const long long gx = (long long)tiles_x * g.n;
-    if (gx > 0x7fffffffLL || g.k > 65535) return hipErrorInvalidConfiguration;
-    dim3 grid((unsigned)gx, 2, (unsigned)g.k);
-    hipLaunchKernelGGL(fht_combine_kernel, grid, dim3(256), 0, stream, sub, g.p, g.W, tiles_x,
-                       tables);
-    return hipGetLastError();
+hipError_t launch_reg_any(int p, const RegRun* runs, int count, hipStream_t stream) {
+    return count == 1 ? launch_reg_p<PixT, 1>(p, runs, count, stream)
+                      : launch_reg_p<PixT, kPack>(p, runs, count, stream);
 }
 
 }  // namespace
@@ -211,11 +472,93 @@ size_t fht_scratch_bytes(const Geometry& g) {
     return (size_t)(g.h >> kRegMaxP) * 2 * (1u << kRegMaxP) * (size_t)g.W * sizeof(int32_t);
 }
 
+hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream) {
+    // Register-kernel runs, launched in packs of equal (row-block height, pixel type).
+    std::vector<RegRun> runs;
+    runs.reserve(count);
+    for (int q = 0; q < count; ++q) {
+        const FhtJobSpec& J = jobs[q];
+        const Geometry& g = J.g;
+        RegRun r;
+        r.img = J.img;
+        r.dtype = J.dtype;
+        r.w = g.w;
+        r.W = g.W;
+        if (g.p <= kRegMaxP) {
+            r.p = g.p;
+            r.blocks = g.k;
+            r.to_table = 1;
+            r.out = J.tables;
+        } else {  // tall bands: 128-row sub-blocks first, then the coarse levels
+            r.p = kRegMaxP;
+            r.blocks = g.h >> kRegMaxP;
+            r.to_table = 0;
+            r.out = static_cast<int32_t*>(J.scratch);
+        }
+        runs.push_back(r);
+    }
+    for (int dtype = 0; dtype < 2; ++dtype) {
+        for (int p = 0; p <= kRegMaxP; ++p) {
+            std::vector<RegRun> group;
+            for (const RegRun& r : runs)
+                if (r.dtype == dtype && r.p == p) group.push_back(r);
+            for (size_t q0 = 0; q0 < group.size(); q0 += kPack) {
+                const int n = (int)std::min<size_t>(kPack, group.size() - q0);
+                hipError_t e = dtype == 0 ? launch_reg_any<uint8_t>(p, group.data() + q0, n, stream)
+                                          : launch_reg_any<uint16_t>(p, group.data() + q0, n, stream);
+                if (e != hipSuccess) return e;
+            }
+        }
+    }
+    // Coarse levels of the tall bands.
+    std::vector<CombineJob> comb;
+    for (int q = 0; q < count; ++q) {
+        const Geometry& g = jobs[q].g;
+        if (g.p <= kRegMaxP) continue;
+        CombineJob c;
+        c.sub = static_cast<const int32_t*>(jobs[q].scratch);
+        c.tables = jobs[q].tables;
+        c.p = g.p;
+        c.W = g.W;
+        c.k = g.k;
+        c.tiles_x = (g.W + 255) / 256;
+        c.item0 = 0;
+        comb.push_back(c);
+    }
+    for (int sh = 1; sh <= 3; ++sh) {
+        std::vector<CombineJob> group;
+        for (const CombineJob& c : comb)
+            if (c.p - kRegMaxP == sh) group.push_back(c);
+        for (size_t q0 = 0; q0 < group.size(); q0 += kPack) {
+            CombinePack pk{};
+            const int n = (int)std::min<size_t>(kPack, group.size() - q0);
+            long long total = 0;
+            for (int q = 0; q < n; ++q) {
+                pk.job[q] = group[q0 + q];
+                pk.job[q].item0 = (int)total;
+                total += (long long)pk.job[q].tiles_x * ((1LL << pk.job[q].p) / kShiftGroup) * 2 *
+                         pk.job[q].k;
+                if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            }
+            pk.count = n;
+            pk.total = (int)total;
+            if (sh == 1)
+                hipLaunchKernelGGL(fht_combine_kernel<1>, dim3((unsigned)total), dim3(256), 0, stream, pk);
+            else if (sh == 2)
+                hipLaunchKernelGGL(fht_combine_kernel<2>, dim3((unsigned)total), dim3(256), 0, stream, pk);
+            else
+                hipLaunchKernelGGL(fht_combine_kernel<3>, dim3((unsigned)total), dim3(256), 0, stream, pk);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_fht(const void* img, int dtype, const Geometry& g, int32_t* tables,
                       void* scratch, hipStream_t stream) {
-    if (dtype == 0)
-        return launch_fht_t(static_cast<const uint8_t*>(img), g, tables, scratch, stream);
-    return launch_fht_t(static_cast<const uint16_t*>(img), g, tables, scratch, stream);
+    FhtJobSpec j{img, dtype, g, tables, scratch};
+    return launch_fht_jobs(&j, 1, stream);
 }
 
 }  // namespace fhtp

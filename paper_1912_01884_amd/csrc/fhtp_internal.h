@@ -24,6 +24,17 @@ constexpr int kRegMaxP = 7;
 // ---- band FHT -------------------------------------------------------------
 // Scratch needed by launch_fht (bytes, 0 when n <= 2^kRegMaxP).
 size_t fht_scratch_bytes(const Geometry& g);
+
+// One image's band FHT.
+struct FhtJobSpec {
+    const void* img;
+    int dtype;  // 0 = uint8, 1 = uint16
+    Geometry g;
+    int32_t* tables;  // [k][D][W]
+    void* scratch;    // fht_scratch_bytes(g)
+};
+// Band tables of several images, launched in packs that share kernels.
+hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream);
 // Writes tables [k][D][W] int32.  dtype 0 = uint8, 1 = uint16.
 hipError_t launch_fht(const void* img, int dtype, const Geometry& g, int32_t* tables,
                       void* scratch, hipStream_t stream);
@@ -41,7 +52,7 @@ struct DpPlan {
 };
 
 struct DpBuffers {
-    int32_t* v[2];            // ping-pong value planes [D][pitch]
+    int32_t* vplanes;         // two value planes [2][D][pitch], used in turn
     void* a;                  // back-pointer planes [k-2][D][pitch]
     unsigned long long* key;  // packed argmax keys, one per workgroup of the last step
     int32_t* win;             // angle windows lo[D], hi[D]
@@ -52,5 +63,17 @@ size_t dp_backptr_bytes(const Geometry& g, bool a16);
 size_t dp_key_count(const Geometry& g);
 hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
                      const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream);
+
+// One image's DP, argmax and walk.
+struct DpJobSpec {
+    const int32_t* tables;  // [k][D][W]
+    Geometry g;
+    DpPlan plan;
+    DpBuffers buf;
+    int32_t* score;
+    int32_t* xs;
+};
+// Several images; images of one window class share every step launch.
+hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t stream);
 
 }  // namespace fhtp

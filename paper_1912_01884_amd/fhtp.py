@@ -32,7 +32,8 @@ ERR_POINT = -9
 EXPORTED = (
     "fhtp_strerror", "fhtp_last_error_detail", "fhtp_version", "fhtp_table_shape",
     "fhtp_fht_workspace_bytes", "fhtp_fht_bands", "fhtp_dp_workspace_bytes", "fhtp_polyline_dp",
-    "fhtp_detect_workspace_bytes", "fhtp_detect_polyline",
+    "fhtp_detect_workspace_bytes", "fhtp_detect_polyline", "fhtp_batch_workspace_bytes",
+    "fhtp_detect_batch",
 )
 
 
@@ -49,6 +50,13 @@ class Bend(C.Structure):
     """fhtp_bend: mode 0 = |d_{i+1}-d_i| <= shift_bound, mode 1 = bend angle <= gamma_rad."""
 
     _fields_ = [("mode", C.c_int32), ("shift_bound", C.c_int32), ("gamma_rad", C.c_double)]
+
+
+class Job(C.Structure):
+    """fhtp_job: one detection of a batch (device pointers inside a host descriptor)."""
+
+    _fields_ = [("img", C.c_void_p), ("dtype", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
+                ("k", C.c_int32), ("bend", Bend), ("score", C.c_void_p), ("xs", C.c_void_p)]
 
 
 def make_bend(bend: Optional[int] = None, gamma: Optional[float] = None) -> Bend:
@@ -84,6 +92,8 @@ def lib() -> C.CDLL:
     L.fhtp_polyline_dp.argtypes = [vp, i32, i32, i32, Bend, vp, sz, vp, vp, vp]
     L.fhtp_detect_workspace_bytes.argtypes = [i32, i32, i32, i32, Bend, szp]
     L.fhtp_detect_polyline.argtypes = [vp, i32, i32, i32, i32, Bend, vp, sz, vp, vp, vp]
+    L.fhtp_batch_workspace_bytes.argtypes = [C.POINTER(Job), i32, szp]
+    L.fhtp_detect_batch.argtypes = [C.POINTER(Job), i32, vp, sz, vp]
     for name in EXPORTED:
         if name not in ("fhtp_strerror", "fhtp_last_error_detail", "fhtp_version"):
             getattr(L, name).restype = C.c_int
@@ -222,3 +232,43 @@ def detect_polyline(img, k: int, bend: Optional[int] = None, gamma: Optional[flo
                                     score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
     _check(rc, "detect_polyline")
     return score, xs
+
+
+def batch_workspace_bytes(jobs) -> int:
+    arr = (Job * len(jobs))(*jobs)
+    out = C.c_size_t()
+    _check(lib().fhtp_batch_workspace_bytes(arr, len(jobs), C.byref(out)), "batch_workspace_bytes")
+    return out.value
+
+
+def make_jobs(images, ks, bends=None, gammas=None, scores=None, xss=None):
+    """Job descriptors for device images; allocates score/xs tensors unless given."""
+    torch = _torch()
+    jobs, keep = [], []
+    for q, img in enumerate(images):
+        _require_device(img, "img")
+        h, w = img.shape
+        k = int(ks[q])
+        g = None if gammas is None else gammas[q]
+        b = make_bend(None if (bends is None or g is not None) else bends[q], g)
+        sc = scores[q] if scores is not None else torch.empty(1, dtype=torch.int32,
+                                                              device=img.device)
+        x = xss[q] if xss is not None else torch.empty(k + 1, dtype=torch.int32, device=img.device)
+        jobs.append(Job(img.data_ptr(), _dtype_code(img), h, w, k, b, sc.data_ptr(), x.data_ptr()))
+        keep.append((sc, x))
+    return jobs, keep
+
+
+def detect_batch(images, ks, bends=None, gammas=None, ws=None, scores=None, xss=None,
+                 stream=None):
+    """Many detections in one call; returns [(score, xs)] device tensors per image."""
+    torch = _torch()
+    if len(images) == 0:
+        return []
+    jobs, keep = make_jobs(images, ks, bends, gammas, scores, xss)
+    nbytes = batch_workspace_bytes(jobs)
+    ws_t, ws_n = _ws(nbytes, images[0].device, ws)
+    arr = (Job * len(jobs))(*jobs)
+    rc = lib().fhtp_detect_batch(arr, len(jobs), _ptr(ws_t), ws_n, _stream_ptr(stream))
+    _check(rc, "detect_batch")
+    return keep

@@ -143,3 +143,34 @@ def test_compute_calls_validate_before_launch():
                                   None) == fhtp.ERR_NULL
     assert L.fhtp_detect_polyline(dummy, 1, 65536, 4, 65536, b, dummy, 1, i32, i32,
                                   None) == fhtp.ERR_OVERFLOW
+
+
+def _job(h, w, k, dtype=0, bend=None, img=256, score=256, xs=256):
+    return fhtp.Job(img, dtype, h, w, k, bend if bend is not None else fhtp.make_bend(1),
+                    score, xs)
+
+
+def test_batch_workspace_is_sum_of_single_workspaces():
+    jobs = [_job(64, 64, 4), _job(1024, 300, 4), _job(256, 100, 8, dtype=1, bend=fhtp.Bend(1, 0, 0.2))]
+    total = fhtp.batch_workspace_bytes(jobs)
+    singles = [fhtp.detect_workspace_bytes(j.dtype, j.h, j.w, j.k, j.bend) for j in jobs]
+    assert total >= sum(singles)
+    assert total <= sum(singles) + 256 * len(jobs)
+    assert fhtp.batch_workspace_bytes([]) == 0
+
+
+def test_batch_rejects_any_invalid_job_before_launch():
+    L = fhtp.lib()
+    good = _job(64, 64, 4)
+    for bad, code in [(_job(12, 8, 4), fhtp.ERR_DIMS), (_job(64, 64, 4, dtype=3), fhtp.ERR_DTYPE),
+                      (_job(64, 64, 4, bend=fhtp.Bend(0, -1, 0.0)), fhtp.ERR_BEND),
+                      (_job(64, 64, 4, img=None), fhtp.ERR_NULL),
+                      (_job(65536, 4, 65536, dtype=1), fhtp.ERR_OVERFLOW)]:
+        arr = (fhtp.Job * 2)(good, bad)
+        out = C.c_size_t()
+        assert L.fhtp_batch_workspace_bytes(arr, 2, C.byref(out)) == code
+        # nothing is launched: the dummy pointers are never touched
+        assert L.fhtp_detect_batch(arr, 2, C.c_void_p(256), 1 << 40, None) == code
+    arr = (fhtp.Job * 1)(good)
+    assert L.fhtp_detect_batch(arr, 1, C.c_void_p(256), 16, None) == fhtp.ERR_WORKSPACE
+    assert L.fhtp_detect_batch(arr, 1, None, 1 << 30, None) == fhtp.ERR_NULL

@@ -1,0 +1,89 @@
+"""Batched detection: every job of a mixed batch equals its single-image result.
+
+The batch mixes image sizes, band heights (including two-pass 256/512-row
+bands), pixel types, band counts (k = 1, 2, many) and every kind of bend
+window; results must be bit-identical to fhtp_detect_polyline on each image
+alone and to the CPU oracle.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_util import announce, host, require_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(seed):
+    return np.random.default_rng([191201884, 111, seed])
+
+
+def _mixed_jobs():
+    rng = _rng(0)
+    jobs = []  # (image, k, bend, gamma)
+    shapes = [(64, 64, 4, np.uint8), (256, 300, 8, np.uint16), (1024, 200, 4, np.uint8),
+              (128, 90, 1, np.uint8), (32, 20, 16, np.uint8), (512, 77, 2, np.uint16),
+              (2048, 50, 4, np.uint8), (96, 33, 3, np.uint8)]
+    kinds = [dict(bend=1), dict(bend=4), dict(bend=8), dict(bend=0), dict(bend=17),
+             dict(bend=1000), dict(gamma=0.3), dict(gamma=math.pi / 2)]
+    for q, (h, w, k, dt) in enumerate(shapes):
+        for kind in kinds[q % 3::3]:
+            top = 255 if dt == np.uint8 else 65535
+            img = rng.integers(0, top + 1, size=(h, w)).astype(dt)
+            jobs.append((img, k, kind.get("bend"), kind.get("gamma")))
+    return jobs
+
+
+def test_mixed_batch_matches_single_and_oracle(orc):
+    from paper_1912_01884_amd import fhtp
+    dev = require_gpu()
+    jobs = _mixed_jobs()
+    imgs = [to_device(j[0], dev) for j in jobs]
+    announce(f"batch of {len(jobs)} mixed jobs")
+    bends = [j[2] for j in jobs]
+    gammas = [j[3] for j in jobs]
+    out = fhtp.detect_batch(imgs, [j[1] for j in jobs], bends=bends, gammas=gammas)
+    torch.cuda.synchronize()
+    for q, (img, k, b, g) in enumerate(jobs):
+        s_b, x_b = host(out[q][0]), host(out[q][1])
+        announce(f"single job {q}: {img.shape} k={k} bend={b} gamma={g}")
+        s1, x1 = fhtp.detect_polyline(imgs[q], k, bend=b, gamma=g)
+        assert np.array_equal(s_b, host(s1)) and np.array_equal(x_b, host(x1)), q
+        want_s, want_x = orc.detect_polyline(img, k, bend=b, gamma=g)
+        assert int(s_b[0]) == want_s, q
+        assert x_b.tolist() == want_x.tolist(), q
+
+
+def test_mixed_size_workload_batch_matches_single():
+    """All 256 images of the mixed-size workload, batched vs one at a time."""
+    from paper_1912_01884_amd import fhtp
+    dev = require_gpu()
+    batch = synth.make_c4_batch(256)
+    imgs = [to_device(s.image, dev) for s in batch]
+    ks = [s.k for s in batch]
+    bends = [s.bend for s in batch]
+    announce("mixed-size workload: 256 images batched")
+    out = fhtp.detect_batch(imgs, ks, bends=bends)
+    torch.cuda.synchronize()
+    for q, s in enumerate(batch):
+        s1, x1 = fhtp.detect_polyline(imgs[q], s.k, bend=s.bend)
+        assert np.array_equal(host(out[q][0]), host(s1)), q
+        assert np.array_equal(host(out[q][1]), host(x1)), q
+
+
+def test_batch_repeat_identical():
+    from paper_1912_01884_amd import fhtp
+    dev = require_gpu()
+    batch = synth.make_c4_batch(40)
+    imgs = [to_device(s.image, dev) for s in batch]
+    announce("batch repeat 40")
+    a = fhtp.detect_batch(imgs, [s.k for s in batch], bends=[s.bend for s in batch])
+    b = fhtp.detect_batch(imgs, [s.k for s in batch], bends=[s.bend for s in batch])
+    torch.cuda.synchronize()
+    for q in range(len(batch)):
+        assert np.array_equal(host(a[q][0]), host(b[q][0]))
+        assert np.array_equal(host(a[q][1]), host(b[q][1]))
