@@ -6,7 +6,7 @@ code with the HIP path.
 """
 
 from .oracle import (  # noqa: F401
-    ERR_NULL, ERR_DIMS, ERR_BEND, ERR_OVERFLOW, ERR_UNSUPPORTED, ERR_DTYPE, ERR_POINT,
+    ERR_NULL, ERR_DIMS, ERR_BEND, ERR_OVERFLOW, ERR_UNSUPPORTED, ERR_DTYPE, ERR_POINT, ERR_OPTION,
     Oracle,
     OracleError,
     lib,
@@ -18,4 +18,7 @@ from .oracle import (  # noqa: F401
     detect_polyline,
     detect_from_top,
     angle_window,
+    detect_through_point,
+    smooth_rows,
+    detect_ex,
 )

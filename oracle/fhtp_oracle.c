@@ -20,7 +20,12 @@
  *     sum), with the bend restriction of Section 2.3, found by the bottom-up
  *     dynamic programme of Sections 2.2-2.3 (eqs. (3)-(4)) with the range
  *     maximum done by a plain scan of every admissible successor, then the
- *     backtrace of eq. (5) and the global choice of the main-problem steps 2-3.
+ *     backtrace of eq. (5) and the global choice of the main-problem steps 2-3;
+ *   - the same optimum restricted to polylines through a given point on a band
+ *     boundary (Sections 2.2-2.3, with the bend bounded at every vertex,
+ *     the point included);
+ *   - row smoothing with an integer binomial kernel (main problem, step 1) and
+ *     the transposed problem for mostly horizontal curves (Fig. 7).
  *
  * Discrete reading (the paper leaves these open; each is stated where used):
  *   - displacements d in [-(n-1), n-1]; table row index d + n - 1;
@@ -41,7 +46,13 @@
  * the whole 64x64 configuration, planted model polylines, the unconstrained
  * special case against a separately coded per-column maximum (Section 2.2),
  * and the fast stage recursion against these direct sums with its exact add
- * count (Section 2.1 complexity).
+ * count (Section 2.1 complexity).  Through-point results: brute force over
+ * the polylines through the point, the maximum over all points of a boundary
+ * equal to the free optimum, and, with the bend unbounded, the paper's own
+ * construction (lower part plus the flipped upper part).  Smoothing: the
+ * identity at radius 0, binomial impulse responses, constant rows, and a
+ * library convolution with edge replication.  Horizontal: planted horizontal
+ * polylines and the library transpose.
  */
 #include <math.h>
 #include <stdint.h>
@@ -59,6 +70,7 @@
 #define OR_ERR_UNSUPPORTED (-7)
 #define OR_ERR_DTYPE (-8)
 #define OR_ERR_POINT (-9)
+#define OR_ERR_OPTION (-10)
 
 #define OR_MAX_N 1024
 #define OR_MAX_W (1 << 20)
@@ -250,11 +262,22 @@ int oracle_angle_window(int n, double gamma, int32_t* lo, int32_t* hi) {
  * (main problem, steps 2-3), and the vertices follow eq. (5):
  * x_{i+1} = x_i + d_i, d_{i+1} = pi_i(x_i, d_i).
  *
- * The optional restriction x0_fixed >= 0 keeps only polylines starting at that
- * column (a top point of the main problem, step 2).
+ * The optional pin (pin_j in [0, k], pin_x) keeps only polylines whose vertex
+ * x_{pin_j} equals pin_x: the extreme polyline through the point (pin_x, pin_j*n)
+ * of Sections 2.2-2.3 ("Subproblem 2/3"), with every bend restricted, including
+ * the one at the point.  pin_j = 0 is a top point of the main problem, step 2.
+ * Vertex x_j is the start of link j (j < k) or the end of link k-1 (j = k), so
+ * the pin masks V_j(x, d) to x = pin_x, or V_{k-1}(x, d) to x + d = pin_x.
  */
+static int pinned_out(int i, int k, int x, int d, int pin_j, int pin_x) {
+    if (pin_j < 0) return 0;
+    if (pin_j == i && i < k) return x != pin_x;
+    if (pin_j == k && i == k - 1) return x + d != pin_x;
+    return 0;
+}
+
 static int dp_core(const int32_t* tables, int h, int w, int k, int mode, int bound, double gamma,
-                   int x0_fixed, int32_t* score, int32_t* xs) {
+                   int pin_j, int pin_x, int32_t* score, int32_t* xs) {
     const int n = h / k;
     const int W = w + n;
     const int D = 2 * n - 1;
@@ -293,7 +316,9 @@ static int dp_core(const int32_t* tables, int h, int w, int k, int mode, int bou
     for (int x = 0; x < w; ++x)
         for (int r = 0; r < D; ++r) {
             int d = r - (n - 1);
-            V[IDX(x, r)] = (x + d >= 0 && x + d < w) ? TAB(k - 1, x, r) : -1;
+            V[IDX(x, r)] = (x + d >= 0 && x + d < w && !pinned_out(k - 1, k, x, d, pin_j, pin_x))
+                               ? TAB(k - 1, x, r)
+                               : -1;
         }
 
     for (int i = k - 2; i >= 0; --i) {
@@ -320,7 +345,9 @@ static int dp_core(const int32_t* tables, int h, int w, int k, int mode, int bou
                         have = 1;
                     }
                 }
-                Vn[IDX(x, r)] = (have && best >= 0) ? TAB(i, x, r) + best : -1;
+                Vn[IDX(x, r)] = (have && best >= 0 && !pinned_out(i, k, x, d, pin_j, pin_x))
+                                    ? TAB(i, x, r) + best
+                                    : -1;
                 pii[IDX(x, r)] = have ? arg : d;
             }
         }
@@ -332,7 +359,6 @@ static int dp_core(const int32_t* tables, int h, int w, int k, int mode, int bou
     int64_t best = -2;
     int bx = 0, bd = 0;
     for (int x = 0; x < w; ++x) {
-        if (x0_fixed >= 0 && x != x0_fixed) continue;
         for (int r = 0; r < D; ++r) {
             int64_t v = V[IDX(x, r)];
             if (v > best) {
@@ -365,11 +391,11 @@ int oracle_polyline_dp(const int32_t* tables, int h, int w, int k, int mode, int
     if (rc != OR_OK && rc != OR_ERR_OVERFLOW) return rc;
     rc = check_bend(mode, bound, gamma);
     if (rc != OR_OK) return rc;
-    return dp_core(tables, h, w, k, mode, bound, gamma, -1, score, xs);
+    return dp_core(tables, h, w, k, mode, bound, gamma, -1, -1, score, xs);
 }
 
 static int detect_common(const void* img, int dtype, int h, int w, int k, int mode, int bound,
-                         double gamma, int x0_fixed, int32_t* score, int32_t* xs) {
+                         double gamma, int pin_j, int pin_x, int32_t* score, int32_t* xs) {
     if (!img || !score || !xs) return OR_ERR_NULL;
     int rc = check_shape(dtype, h, w, k);
     if (rc != OR_OK) return rc;
@@ -380,19 +406,119 @@ static int detect_common(const void* img, int dtype, int h, int w, int k, int mo
     int32_t* tables = (int32_t*)malloc(sizeof(int32_t) * cells);
     if (!tables) return OR_ERR_UNSUPPORTED;
     rc = oracle_fht_bands(img, dtype, h, w, k, tables);
-    if (rc == OR_OK) rc = dp_core(tables, h, w, k, mode, bound, gamma, x0_fixed, score, xs);
+    if (rc == OR_OK) rc = dp_core(tables, h, w, k, mode, bound, gamma, pin_j, pin_x, score, xs);
     free(tables);
     return rc;
 }
 
 int oracle_detect_polyline(const void* img, int dtype, int h, int w, int k, int mode, int bound,
                            double gamma, int32_t* score, int32_t* xs) {
-    return detect_common(img, dtype, h, w, k, mode, bound, gamma, -1, score, xs);
+    return detect_common(img, dtype, h, w, k, mode, bound, gamma, -1, -1, score, xs);
 }
 
 /* Best polyline whose first vertex is the top point (x0, 0) (main problem, step 2). */
 int oracle_detect_from_top(const void* img, int dtype, int h, int w, int k, int mode, int bound,
                            double gamma, int x0, int32_t* score, int32_t* xs) {
     if (x0 < 0 || x0 >= w) return OR_ERR_POINT;
-    return detect_common(img, dtype, h, w, k, mode, bound, gamma, x0, score, xs);
+    return detect_common(img, dtype, h, w, k, mode, bound, gamma, 0, x0, score, xs);
+}
+
+/* Best polyline through the point (pin_x, row pin_j*n), pin_j in [0, k]
+ * (Sections 2.2-2.3, a point on a band boundary; pin_j = k is the last row). */
+int oracle_detect_through_point(const void* img, int dtype, int h, int w, int k, int mode,
+                                int bound, double gamma, int pin_j, int pin_x, int32_t* score,
+                                int32_t* xs) {
+    if (!img || !score || !xs) return OR_ERR_NULL;
+    int rc = check_shape(dtype, h, w, k);
+    if (rc != OR_OK) return rc;
+    if (pin_j < 0 || pin_j > k || pin_x < 0 || pin_x >= w) return OR_ERR_POINT;
+    return detect_common(img, dtype, h, w, k, mode, bound, gamma, pin_j, pin_x, score, xs);
+}
+
+/*
+ * Row-wise smoothing before the transform (main problem, step 1: each image
+ * row is convolved with a one-dimensional Gaussian).  Integer reading: the
+ * binomial kernel C(2r, i), i = 0..2r (variance r/2), with the row extended by
+ * repeating its end pixels, normalised by 4^r with rounding half up:
+ *   out(y, x) = (sum_i C(2r, i) * pixel(y, clamp(x + i - r)) + 4^r / 2) >> 2r,
+ * r = 0 leaves the image unchanged.  Output has the input's pixel type.
+ */
+int oracle_smooth_rows(const void* img, int dtype, int h, int w, int radius, void* out) {
+    if (!img || !out) return OR_ERR_NULL;
+    if (dtype != 0 && dtype != 1) return OR_ERR_DTYPE;
+    if (h <= 0 || w <= 0) return OR_ERR_DIMS;
+    if (radius < 0 || radius > 7) return OR_ERR_OPTION;
+    int64_t coef[15];
+    const int L = 2 * radius + 1;
+    coef[0] = 1;
+    for (int i = 1; i < L; ++i) coef[i] = coef[i - 1] * (2 * radius - i + 1) / i;
+    const int64_t half = radius > 0 ? ((int64_t)1 << (2 * radius - 1)) : 0;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < h; ++y) {
+        for (int x = 0; x < w; ++x) {
+            int64_t acc = 0;
+            for (int i = 0; i < L; ++i) {
+                int c = x + i - radius;
+                if (c < 0) c = 0;
+                if (c >= w) c = w - 1;
+                acc += coef[i] * pixel(img, dtype, w, y, c);
+            }
+            const int64_t v = (acc + half) >> (2 * radius);
+            if (dtype == 0)
+                ((uint8_t*)out)[(int64_t)y * w + x] = (uint8_t)v;
+            else
+                ((uint16_t*)out)[(int64_t)y * w + x] = (uint16_t)v;
+        }
+    }
+    return OR_OK;
+}
+
+/*
+ * The detector with its optional steps, in this order:
+ *   1. orientation 1, mostly horizontal curves (Fig. 7): the image is
+ *      transposed, so the k bands become vertical strips of w/k columns and
+ *      the result gives the row of the curve on each strip boundary;
+ *   2. row smoothing with radius smooth_radius (main problem, step 1), along
+ *      the rows of the (possibly transposed) image, i.e. across the curve;
+ *   3. the polyline search, through the point (pin_x, pin_j * n) when
+ *      pin_j >= 0, else over every polyline.
+ * h, w are the dimensions of the image as given; xs receives k + 1 entries.
+ */
+int oracle_detect_ex(const void* img, int dtype, int h, int w, int k, int mode, int bound,
+                     double gamma, int smooth_radius, int orientation, int pin_j, int pin_x,
+                     int32_t* score, int32_t* xs) {
+    if (!img || !score || !xs) return OR_ERR_NULL;
+    if (dtype != 0 && dtype != 1) return OR_ERR_DTYPE;
+    if (h <= 0 || w <= 0) return OR_ERR_DIMS;
+    if (orientation != 0 && orientation != 1) return OR_ERR_OPTION;
+    if (smooth_radius < 0 || smooth_radius > 7) return OR_ERR_OPTION;
+    const int hh = orientation ? w : h, ww = orientation ? h : w;
+    int rc = check_shape(dtype, hh, ww, k);
+    if (rc != OR_OK) return rc;
+    if (pin_j >= 0 && (pin_j > k || pin_x < 0 || pin_x >= ww)) return OR_ERR_POINT;
+    const size_t bpp = dtype == 0 ? 1 : 2;
+    const size_t bytes = bpp * (size_t)h * (size_t)w;
+    unsigned char* t = (unsigned char*)malloc(bytes);
+    unsigned char* sm = (unsigned char*)malloc(bytes);
+    if (!t || !sm) {
+        free(t);
+        free(sm);
+        return OR_ERR_UNSUPPORTED;
+    }
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            const size_t src = (size_t)y * w + x;
+            const size_t dst = orientation ? (size_t)x * h + y : src;
+            if (dtype == 0)
+                t[dst] = ((const uint8_t*)img)[src];
+            else
+                ((uint16_t*)t)[dst] = ((const uint16_t*)img)[src];
+        }
+    rc = oracle_smooth_rows(t, dtype, hh, ww, smooth_radius, sm);
+    if (rc == OR_OK)
+        rc = detect_common(sm, dtype, hh, ww, k, mode, bound, gamma, pin_j, pin_j >= 0 ? pin_x : -1,
+                           score, xs);
+    free(t);
+    free(sm);
+    return rc;
 }

@@ -25,6 +25,7 @@ ERR_OVERFLOW = -4
 ERR_UNSUPPORTED = -7
 ERR_DTYPE = -8
 ERR_POINT = -9
+ERR_OPTION = -10
 
 
 class OracleError(RuntimeError):
@@ -76,9 +77,18 @@ class Oracle:
         L.oracle_detect_from_top.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                                              C.c_int, C.c_int, C.c_double, C.c_int, i32p, i32p]
         L.oracle_angle_window.argtypes = [C.c_int, C.c_double, i32p, i32p]
+        L.oracle_detect_through_point.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                                  C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                                  i32p, i32p]
+        L.oracle_smooth_rows.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.c_void_p]
+        L.oracle_detect_ex.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                       C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
+                                       i32p, i32p]
         for f in (L.oracle_dyadic_pattern, L.oracle_table_shape, L.oracle_fht_bands,
                   L.oracle_polyline_dp, L.oracle_detect_polyline, L.oracle_detect_from_top,
-                  L.oracle_angle_window):
+                  L.oracle_angle_window, L.oracle_detect_through_point, L.oracle_smooth_rows,
+                  L.oracle_detect_ex):
             f.restype = C.c_int
         self.L = L
         self.path = path
@@ -142,6 +152,44 @@ class Oracle:
         _check(rc, "detect_from_top")
         return int(score[0]), xs
 
+    def detect_through_point(self, img: np.ndarray, k: int, pin_j: int, pin_x: int,
+                             bend: int = None, gamma: float = None) -> Tuple[int, np.ndarray]:
+        img = np.ascontiguousarray(img)
+        h, w = img.shape
+        mode, b, g = _bend_args(bend, gamma)
+        score = np.zeros(1, dtype=np.int32)
+        xs = np.zeros(k + 1, dtype=np.int32)
+        rc = self.L.oracle_detect_through_point(img.ctypes.data, _dtype_code(img), h, w, k, mode,
+                                                b, g, int(pin_j), int(pin_x), _i32p(score),
+                                                _i32p(xs))
+        _check(rc, "detect_through_point")
+        return int(score[0]), xs
+
+    def smooth_rows(self, img: np.ndarray, radius: int) -> np.ndarray:
+        img = np.ascontiguousarray(img)
+        h, w = img.shape
+        out = np.zeros_like(img)
+        rc = self.L.oracle_smooth_rows(img.ctypes.data, _dtype_code(img), h, w, int(radius),
+                                       out.ctypes.data)
+        _check(rc, "smooth_rows")
+        return out
+
+    def detect_ex(self, img: np.ndarray, k: int, bend: int = None, gamma: float = None,
+                  smooth_radius: int = 0, horizontal: bool = False, pin=None
+                  ) -> Tuple[int, np.ndarray]:
+        """Detector with its options; pin = (boundary j, column) or None."""
+        img = np.ascontiguousarray(img)
+        h, w = img.shape
+        mode, b, g = _bend_args(bend, gamma)
+        pj, px = (-1, -1) if pin is None else (int(pin[0]), int(pin[1]))
+        score = np.zeros(1, dtype=np.int32)
+        xs = np.zeros(max(k, 0) + 1, dtype=np.int32)
+        rc = self.L.oracle_detect_ex(img.ctypes.data, _dtype_code(img), h, w, k, mode, b, g,
+                                     int(smooth_radius), int(bool(horizontal)), pj, px,
+                                     _i32p(score), _i32p(xs))
+        _check(rc, "detect_ex")
+        return int(score[0]), xs
+
     def angle_window(self, n: int, gamma: float) -> Tuple[np.ndarray, np.ndarray]:
         lo = np.zeros(2 * n - 1, dtype=np.int32)
         hi = np.zeros(2 * n - 1, dtype=np.int32)
@@ -193,3 +241,16 @@ def detect_from_top(img, k, x0, bend=None, gamma=None):
 
 def angle_window(n, gamma):
     return lib().angle_window(n, gamma)
+
+
+def detect_through_point(img, k, pin_j, pin_x, bend=None, gamma=None):
+    return lib().detect_through_point(img, k, pin_j, pin_x, bend=bend, gamma=gamma)
+
+
+def smooth_rows(img, radius):
+    return lib().smooth_rows(img, radius)
+
+
+def detect_ex(img, k, bend=None, gamma=None, smooth_radius=0, horizontal=False, pin=None):
+    return lib().detect_ex(img, k, bend=bend, gamma=gamma, smooth_radius=smooth_radius,
+                           horizontal=horizontal, pin=pin)

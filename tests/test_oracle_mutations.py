@@ -16,6 +16,7 @@ import pytest
 import oracle
 from oracle import build as obuild
 from tests import test_oracle_dp as tdp
+from tests import test_oracle_options as topt
 from tests import test_oracle_pattern as tpat
 from tests import test_oracle_tables as ttab
 
@@ -25,14 +26,24 @@ MUTANTS = {
     "tables_clamp_not_wrap": ("if (c >= W) c -= W;", "if (c >= W) c = W - 1;"),
     "tables_left_lines_lean_right": ("const int sigma = d < 0 ? -1 : 1;", "const int sigma = 1;"),
     "dp_tie_largest_successor": ("if (!have || v > best) {", "if (!have || v >= best) {"),
-    "dp_no_feasibility_check": ("(have && best >= 0) ? TAB(i, x, r) + best : -1",
-                                "have ? TAB(i, x, r) + best : -1"),
+    "dp_no_feasibility_check": ("(have && best >= 0 && !pinned_out(i, k, x, d, pin_j, pin_x))",
+                                "(have && !pinned_out(i, k, x, d, pin_j, pin_x))"),
     "dp_window_too_narrow": ("return diff <= bound;", "return diff < bound;"),
-    "dp_last_band_unmasked": ("V[IDX(x, r)] = (x + d >= 0 && x + d < w) ? TAB(k - 1, x, r) : -1;",
-                              "V[IDX(x, r)] = TAB(k - 1, x, r);"),
+    "dp_last_band_unmasked": ("(x + d >= 0 && x + d < w && !pinned_out(k - 1, k, x, d, pin_j, pin_x))",
+                              "(!pinned_out(k - 1, k, x, d, pin_j, pin_x))"),
     "argmax_tie_last": ("            if (v > best) {\n                best = v;\n                bx = x;",
                         "            if (v >= best) {\n                best = v;\n                bx = x;"),
     "backtrace_last_vertex": ("xs[k] = x + d;", "xs[k] = x;"),
+    "pin_last_vertex_is_link_start": ("return x + d != pin_x;", "return x != pin_x;"),
+    "pin_one_band_late": ("if (pin_j == i && i < k) return x != pin_x;",
+                          "if (pin_j == i + 1 && i < k) return x != pin_x;"),
+    "smooth_truncates": ("const int64_t v = (acc + half) >> (2 * radius);",
+                         "const int64_t v = acc >> (2 * radius);"),
+    "smooth_reflects_edge": ("if (c < 0) c = 0;", "if (c < 0) c = -c;"),
+    "smooth_wrong_coefficients": ("coef[i] = coef[i - 1] * (2 * radius - i + 1) / i;",
+                                  "coef[i] = coef[i - 1] * (2 * radius - i + 2) / (i + 1);"),
+    "horizontal_not_transposed": ("const size_t dst = orientation ? (size_t)x * h + y : src;",
+                                  "const size_t dst = src;"),
     "angle_drop_cross_term": ("tan_gamma * ((double)n * (double)n + (double)d * (double)dp)",
                               "tan_gamma * ((double)n * (double)n)"),
 }
@@ -59,6 +70,16 @@ def _pins():
         ("angle_windows", tdp.test_angle_window_properties),
         ("escaping_streak", lambda o: [tdp.test_escaping_streak_is_infeasible(o, b)
                                        for b in (0, 1)]),
+        ("through_brute", lambda o: [topt.test_through_point_brute_force_mode0(o, *a)
+                                     for a in [(2, 2, 4), (4, 3, 5), (4, 1, 7)]]),
+        ("through_halves", lambda o: topt.test_unbounded_bend_equals_paper_halves(o, 0)),
+        ("smooth_impulse", lambda o: [topt.test_smoothing_impulse_response_is_binomial(o, r)
+                                      for r in (1, 3)]),
+        ("smooth_library", lambda o: topt.test_smoothing_matches_library_convolution(
+            o, 2, np.uint8)),
+        ("smooth_narrow", topt.test_smoothing_narrow_rows),
+        ("horizontal", lambda o: topt.test_horizontal_is_the_transposed_problem(o, 0)),
+        ("horizontal_planted", lambda o: topt.test_planted_horizontal_polyline(o, 0)),
     ]
 
 
