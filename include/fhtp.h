@@ -83,6 +83,7 @@ typedef struct {
 #define FHTP_ERR_UNSUPPORTED (-7) /* valid request this build does not implement */
 #define FHTP_ERR_DTYPE (-8)       /* dtype is not FHTP_U8 or FHTP_U16 */
 #define FHTP_ERR_POINT (-9)       /* through-point query outside the image or band grid */
+#define FHTP_ERR_OPTION (-10)     /* an option of fhtp_options is out of range */
 
 /* Human-readable name of an error code (static storage). */
 const char* fhtp_strerror(int code);
@@ -142,6 +143,61 @@ int fhtp_detect_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend
                                 size_t* bytes);
 int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
                          void* ws, size_t ws_bytes, int32_t* score, int32_t* xs, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * The detector with its optional steps (all off when opt is NULL or zeroed
+ * with pin_boundary = -1), applied in this order:
+ *
+ *   horizontal = 1: mostly horizontal curves (Fig. 7).  The detector runs on
+ *       the transposed image: the k bands are vertical strips of w/k columns
+ *       (w/k a power of two <= 1024, h <= 2^20, w * maxval < 2^31), links run
+ *       left to right, and xs[i] is the ROW of the curve on column i*n
+ *       (xs[k] on column w-1).
+ *   smooth_radius = r in [0, 7]: each row of the detection image (each
+ *       column of the input when horizontal, i.e. always across the curve) is
+ *       smoothed before the transform (main problem, step 1).  The Gaussian is
+ *       read as the binomial kernel C(2r, i) / 4^r, i = 0..2r (variance r/2),
+ *       rows extended by repeating their end pixels, rounded half up:
+ *         out(y, x) = (sum_i C(2r, i) * in(y, clamp(x + i - r)) + 4^r/2) >> 2r.
+ *       The result keeps the pixel type; r = 0 skips the step.
+ *   pin_boundary = j in [0, k], pin_pos = p: only polylines through the
+ *       point on band boundary j at position p (a column, or a row when
+ *       horizontal) compete: x_j = p (Sections 2.2-2.3, "Subproblems 2-3";
+ *       j = 0 is a top point as in main-problem step 2, j = k the last row).
+ *       The bend bound holds at every vertex, the point included, so this is
+ *       the exact best polyline through the point.  With an unbounded bend it
+ *       equals the paper's construction (best lower part from the point plus
+ *       the best upper part of the flipped bands above it).  pin_boundary = -1
+ *       leaves every polyline free.
+ *
+ * img: device [h][w] as fhtp_detect_polyline (h, w of the image as stored).
+ * ws:  device scratch, fhtp_detect_ex_workspace_bytes(...) bytes (it holds the
+ *      transposed / smoothed image when either step is on, then the tables).
+ * Errors: FHTP_ERR_OPTION for horizontal not in {0,1} or r outside [0,7];
+ *         FHTP_ERR_POINT for j outside [-1, k] or p outside the image;
+ *         FHTP_ERR_DIMS / _OVERFLOW checked on the detection image.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t smooth_radius; /* 0 .. 7 */
+    int32_t horizontal;    /* 0: mostly vertical curves, 1: mostly horizontal */
+    int32_t pin_boundary;  /* -1: no point; else the band boundary j in [0, k] */
+    int32_t pin_pos;       /* column (vertical) or row (horizontal) of the point */
+} fhtp_options;
+
+/* The detection image alone (the first two optional steps above), for callers
+ * that keep it or run the stages themselves:
+ *   out = smooth_rows(horizontal ? transpose(img) : img, smooth_radius)
+ * img: device [h][w] of dtype; out: device [w][h] when horizontal, else
+ * [h][w], same dtype, must not overlap img.  h, w in [1, 2^24].
+ * Errors: FHTP_ERR_NULL, FHTP_ERR_DTYPE, FHTP_ERR_DIMS, FHTP_ERR_OPTION. */
+int fhtp_prepare_image(const void* img, fhtp_dtype dtype, int h, int w, int smooth_radius,
+                       int horizontal, void* out, void* stream);
+
+int fhtp_detect_ex_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
+                                   const fhtp_options* opt, size_t* bytes);
+int fhtp_detect_polyline_ex(const void* img, fhtp_dtype dtype, int h, int w, int k,
+                            fhtp_bend bend, const fhtp_options* opt, void* ws, size_t ws_bytes,
+                            int32_t* score, int32_t* xs, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Many detections in one call: images of different h, w, k, pixel type and

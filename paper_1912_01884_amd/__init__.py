@@ -11,5 +11,6 @@ from . import fhtp  # noqa: F401
 from .fhtp import (  # noqa: F401
     Bend, FhtpError, make_bend, table_shape, fht_bands, polyline_dp, detect_polyline,
     fht_workspace_bytes, dp_workspace_bytes, detect_workspace_bytes, detect_batch,
-    batch_workspace_bytes, Job,
+    batch_workspace_bytes, Job, Options, make_options, detect_polyline_ex,
+    detect_ex_workspace_bytes, prepare_image,
 )

@@ -163,6 +163,7 @@ const char* fhtp_strerror(int code) {
         case FHTP_ERR_UNSUPPORTED: return "unsupported request";
         case FHTP_ERR_DTYPE: return "invalid pixel type";
         case FHTP_ERR_POINT: return "point outside the image or band grid";
+        case FHTP_ERR_OPTION: return "option out of range";
         default: return "unknown error";
     }
 }
@@ -268,6 +269,98 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
     if (rc != FHTP_OK) return rc;
     return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(base, L.dp), score, xs, s),
                       "detect_polyline/dp");
+}
+
+namespace {
+
+constexpr int kMaxSmoothRadius = 7;
+
+// Validated extended request: the detection image's geometry and where the
+// prepared image (if any) sits in the workspace.
+struct ExPlan {
+    fhtp::Geometry g;
+    fhtp::DpPlan pl;
+    fhtp::Pin pin;
+    bool prep;          // transpose and/or smoothing writes a detection image
+    size_t prep_bytes;  // its size, aligned
+    DetectLayout L;     // offsets relative to the end of the prepared image
+};
+
+int plan_ex(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend, const fhtp_options* opt,
+            ExPlan* e) {
+    fhtp_options o{0, 0, -1, 0};
+    if (opt) o = *opt;
+    if (o.horizontal != 0 && o.horizontal != 1) return FHTP_ERR_OPTION;
+    if (o.smooth_radius < 0 || o.smooth_radius > kMaxSmoothRadius) return FHTP_ERR_OPTION;
+    const int hh = o.horizontal ? w : h, ww = o.horizontal ? h : w;
+    int rc = shape(hh, ww, k, &e->g);
+    if (rc == FHTP_OK) rc = pixels(dtype, hh);
+    if (rc == FHTP_OK) rc = plan(e->g, bend, &e->pl);
+    if (rc != FHTP_OK) return rc;
+    if (o.pin_boundary < -1 || o.pin_boundary > k) return FHTP_ERR_POINT;
+    if (o.pin_boundary >= 0 && (o.pin_pos < 0 || o.pin_pos >= ww)) return FHTP_ERR_POINT;
+    e->pin.j = o.pin_boundary;
+    e->pin.x = o.pin_boundary >= 0 ? o.pin_pos : 0;
+    e->prep = o.horizontal || o.smooth_radius > 0;
+    const size_t bpp = dtype == FHTP_U8 ? 1 : 2;
+    e->prep_bytes = e->prep ? align_up((size_t)h * (size_t)w * bpp) : 0;
+    e->L = detect_layout(e->g, e->pl);
+    return FHTP_OK;
+}
+
+}  // namespace
+
+int fhtp_prepare_image(const void* img, fhtp_dtype dtype, int h, int w, int smooth_radius,
+                       int horizontal, void* out, void* stream) {
+    if (!img || !out) return FHTP_ERR_NULL;
+    if (dtype != FHTP_U8 && dtype != FHTP_U16) return FHTP_ERR_DTYPE;
+    if (h <= 0 || w <= 0 || h > (1 << 24) || w > (1 << 24)) return FHTP_ERR_DIMS;
+    if (horizontal != 0 && horizontal != 1) return FHTP_ERR_OPTION;
+    if (smooth_radius < 0 || smooth_radius > kMaxSmoothRadius) return FHTP_ERR_OPTION;
+    (void)hipGetLastError();
+    return hip_status(fhtp::launch_prep(img, (int)dtype, h, w, smooth_radius, horizontal, out,
+                                        static_cast<hipStream_t>(stream)),
+                      "prepare_image");
+}
+
+int fhtp_detect_ex_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
+                                   const fhtp_options* opt, size_t* bytes) {
+    if (!bytes) return FHTP_ERR_NULL;
+    ExPlan e;
+    const int rc = plan_ex(dtype, h, w, k, bend, opt, &e);
+    if (rc != FHTP_OK) return rc;
+    *bytes = e.prep_bytes + e.L.dp.end;
+    return FHTP_OK;
+}
+
+int fhtp_detect_polyline_ex(const void* img, fhtp_dtype dtype, int h, int w, int k,
+                            fhtp_bend bend, const fhtp_options* opt, void* ws, size_t ws_bytes,
+                            int32_t* score, int32_t* xs, void* stream) {
+    if (!img || !score || !xs) return FHTP_ERR_NULL;
+    ExPlan e;
+    int rc = plan_ex(dtype, h, w, k, bend, opt, &e);
+    if (rc != FHTP_OK) return rc;
+    rc = check_ws(ws, ws_bytes, e.prep_bytes + e.L.dp.end);
+    if (rc != FHTP_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    const void* det = img;
+    (void)hipGetLastError();
+    if (e.prep) {
+        rc = hip_status(fhtp::launch_prep(img, (int)dtype, h, w, opt->smooth_radius,
+                                          opt->horizontal, base, s),
+                        "detect_polyline_ex/prep");
+        if (rc != FHTP_OK) return rc;
+        det = base;
+        base += e.prep_bytes;
+    }
+    int32_t* tables = reinterpret_cast<int32_t*>(base + e.L.tables);
+    rc = hip_status(fhtp::launch_fht(det, (int)dtype, e.g, tables, base + e.L.scratch, s),
+                    "detect_polyline_ex/fht");
+    if (rc != FHTP_OK) return rc;
+    return hip_status(fhtp::launch_dp(tables, e.g, e.pl, dp_buffers(base, e.L.dp), score, xs, s,
+                                      e.pin),
+                      "detect_polyline_ex/dp");
 }
 
 namespace {

@@ -27,6 +27,12 @@
 // from V_1, and later ones are read two bands per memory round trip by loading
 // every candidate of the next band speculatively.
 //
+// A query through a point (Sections 2.2-2.3) pins vertex x_j to one column:
+// the step that makes V_j marks every cell of another column infeasible, and
+// a pin on x_{k-1} or x_k (cells of V_{k-1} with x or x + d off the point) is
+// applied where the table H_{k-1} is read as V_{k-1}.  Every other bend stays
+// bounded as usual, so the result is the best polyline through the point.
+//
 // Every launch takes a pack of images (jobs).  An image with k bands takes
 // part in the step launches s = 0 .. k-2 of its pack (band i = k-2-s), so a
 // batch of images of different sizes shares one launch per step instead of one
@@ -58,6 +64,9 @@ struct DpJob {
     int full;     // windows cover every displacement
     int items_x;  // workgroups along x
     int item0;    // first workgroup of this image in the launch
+    int vin_pin;  // pin on the cells read from vin: 0 none, 1 x' == pin, 2 x' + d' == pin
+    int vin_pin_x;
+    int out_pin_x;  // V_i cells with x != out_pin_x are infeasible (-1: no pin)
 };
 
 // CAP images per launch: 1 for a single image (small kernel arguments, which
@@ -81,6 +90,7 @@ struct WalkJob {
     int n_keys, vin_pitch, a_pitch;
     int n, w, k;
     int bound, full;
+    int vin_pin, vin_pin_x;  // as DpJob, for the cells read from vin
 };
 
 template <int CAP>
@@ -111,14 +121,33 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// Feasible cells (x', d') of V_{i+1}: x' in [xlo, xlo + xlen) and x' + d' in
+// [tlo, tlo + tlen).  Without a pin both ranges are [0, w).
+struct VMask {
+    int xlo, xlen, tlo, tlen;
+};
+
+__device__ __forceinline__ VMask vmask(int w, int pin, int pin_x) {
+    VMask m{0, w, 0, w};
+    if (pin == 1) {
+        m.xlo = pin_x;
+        m.xlen = 1;
+    } else if (pin == 2) {
+        m.tlo = pin_x;
+        m.tlen = 1;
+    }
+    return m;
+}
+
 // V_{i+1}(x', d') with the feasibility mask: zero-based row r' = d' + n - 1.
 // The load is unconditional (masked lanes read element 0, which always
 // exists) so that every load of a thread can be in flight at once.
 __device__ __forceinline__ int load_v(const int32_t* __restrict__ vin, int pitch, int xp, int dp,
-                                      int n, int w) {
+                                      int n, const VMask& mk) {
     const int r = dp + n - 1;
-    const bool ok = (unsigned)xp < (unsigned)w && (unsigned)r < (unsigned)(2 * n - 1) &&
-                    (unsigned)(xp + dp) < (unsigned)w;
+    const bool ok = (unsigned)(xp - mk.xlo) < (unsigned)mk.xlen &&
+                    (unsigned)r < (unsigned)(2 * n - 1) &&
+                    (unsigned)(xp + dp - mk.tlo) < (unsigned)mk.tlen;
     const unsigned int off = ok ? (unsigned int)r * (unsigned int)pitch + (unsigned int)xp : 0u;
     const int v = vin[off];
     return ok ? v : -1;
@@ -165,7 +194,7 @@ __device__ __forceinline__ void emit(const DpJob& a, int m, int ra, int hval, in
             (AT)(ra < 0 ? 0 : ra);
     const int x = xp - d;
     if (x < 0 || x >= w) return;
-    const int val = m >= 0 ? hval + m : -1;
+    const int val = (m >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hval + m : -1;
     if (last) {
         const unsigned long long kk = pack_key(val, x, r, D);
         best = kk > best ? kk : best;
@@ -207,9 +236,10 @@ __device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx,
     int hv[DC];
 #pragma unroll
     for (int j = 0; j < DC; ++j) hv[j] = load_h(a, xp, d0 + j);
+    const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
     int v[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = load_v(a.vin, a.vin_pitch, xp, d0 - B + j, n, w);
+    for (int j = 0; j < NV; ++j) v[j] = load_v(a.vin, a.vin_pitch, xp, d0 - B + j, n, mk);
 
     // Suffix maxima inside window-length blocks (smallest index on ties).
     int sv[NV], si[NV];
@@ -272,13 +302,14 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     const int chunk = by * kWaves + wave;
     const int d0 = -(n - 1) + chunk * kDCGeneric;
     const int D = 2 * n - 1;
+    const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
     unsigned long long best = 0;
     if (a.full) {
         // Section 2.2: every d shares the maximum of the whole successor column.
-        int m = load_v(a.vin, a.vin_pitch, xp, -(n - 1), n, w);
+        int m = load_v(a.vin, a.vin_pitch, xp, -(n - 1), n, mk);
         int ia = -(n - 1);
         for (int dp = -(n - 1) + 1; dp <= n - 1; ++dp) {
-            const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
+            const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, mk);
             if (vv > m) {
                 m = vv;
                 ia = dp;
@@ -292,10 +323,10 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
             if (d + n - 1 >= D) break;
             int lo, hi;
             window_of(n, a.full, a.win, a.bound, d, lo, hi);
-            int m = load_v(a.vin, a.vin_pitch, xp, lo, n, w);
+            int m = load_v(a.vin, a.vin_pitch, xp, lo, n, mk);
             int ia = lo;
             for (int dp = lo + 1; dp <= hi; ++dp) {
-                const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, w);
+                const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, mk);
                 if (vv > m) {
                     m = vv;
                     ia = dp;
@@ -307,7 +338,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     finish(a, best, local);
 }
 
-// k = 1: the answer is the best masked cell of H_0 (htab).
+// k = 1: the answer is the best masked cell of H_0 (htab), pinned as vin.
 template <int CAP>
 __global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
     const int jj = dp_find_job(pk, blockIdx.x);
@@ -319,11 +350,14 @@ __global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
     const int x = bx * 64 + lane;
     const int chunk = by * kWaves + wave;
     const int D = 2 * n - 1;
+    const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
     unsigned long long best = 0;
     for (int j = 0; j < kDCGeneric; ++j) {
         const int r = chunk * kDCGeneric + j;
         const int d = r - (n - 1);
-        if (r >= D || x >= w || x + d < 0 || x + d >= w) continue;
+        if (r >= D || (unsigned)(x - mk.xlo) >= (unsigned)mk.xlen ||
+            (unsigned)(x + d - mk.tlo) >= (unsigned)mk.tlen)
+            continue;
         const unsigned long long kk = pack_key(a.htab[(size_t)r * a.h_pitch + x], x, r, D);
         best = kk > best ? kk : best;
     }
@@ -370,10 +404,11 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
         }
         int lo, hi;
         window_of(n, a.full, a.win, a.bound, r - (n - 1), lo, hi);
+        const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
         unsigned long long bestk = 0;
         for (int base = lo; base <= hi; base += 64) {
             const int dp = base + lane;
-            const int v = load_v(a.vin, a.vin_pitch, x1, dp, n, w);
+            const int v = load_v(a.vin, a.vin_pitch, x1, dp, n, mk);
             const unsigned long long kk =
                 dp <= hi ? ((unsigned long long)(unsigned int)(v + 2) << 32) |
                                (unsigned long long)(0xffffffffu - (unsigned int)(dp + n - 1))
@@ -520,6 +555,13 @@ hipError_t launch_step(const DpClass& c, hipStream_t s, const DpPack<CAP>& pk) {
 #undef FHTP_B
 }
 
+// Pin on V_{k-1} read from the table H_{k-1}: x_{k-1} is the column of the
+// cell, x_k its column plus its displacement.
+void first_step_pin(const DpJobSpec& J, int& mode, int& x) {
+    mode = J.pin.j == J.g.k - 1 ? 1 : J.pin.j == J.g.k ? 2 : 0;
+    x = mode ? J.pin.x : 0;
+}
+
 // Common fields of an image's step descriptor.
 DpJob base_job(const DpJobSpec& J) {
     const Geometry& g = J.g;
@@ -533,6 +575,7 @@ DpJob base_job(const DpJobSpec& J) {
     a.v_pitch = g.pitch;
     a.a_pitch = g.pitch;
     a.items_x = (g.w + 63) / 64;
+    a.out_pin_x = -1;
     return a;
 }
 
@@ -562,6 +605,8 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
             a.vout = last ? nullptr : J->buf.vplanes + (size_t)(i & 1) * plane;
             a.aout = last ? nullptr : static_cast<AT*>(J->buf.a) + (size_t)(i - 1) * plane;
             a.key = last ? J->buf.key : nullptr;
+            if (st == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);
+            a.out_pin_x = J->pin.j == i ? J->pin.x : -1;
             a.item0 = (int)total;
             total += (long long)a.items_x * items_y_of(g, c.dc);
             if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
@@ -601,6 +646,9 @@ hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
             a.win = J.plan.kind == WindowKind::Angle ? J.buf.win : nullptr;
             a.score = J.score;
             a.xs = J.xs;
+            a.vin_pin = 0;
+            a.vin_pin_x = 0;
+            if (g.k == 2) first_step_pin(J, a.vin_pin, a.vin_pin_x);
         }
         pk.count = cnt;
         hipLaunchKernelGGL((walk<AT, CAP>), dim3(cnt), dim3(64), 0, s, pk);
@@ -625,6 +673,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
             DpJob a = base_job(J);
             a.htab = J.tables;
             a.key = J.buf.key;
+            first_step_pin(J, a.vin_pin, a.vin_pin_x);
             a.item0 = (int)total;
             total += (long long)a.items_x * items_y_of(J.g, kDCGeneric);
             if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
@@ -697,8 +746,9 @@ hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t s) {
 }
 
 hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
-                     const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream) {
-    DpJobSpec j{tables, g, plan, buf, score, xs};
+                     const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream,
+                     Pin pin) {
+    DpJobSpec j{tables, g, plan, buf, score, xs, pin};
     return launch_dp_jobs(&j, 1, stream);
 }
 

@@ -58,11 +58,18 @@ struct DpBuffers {
     int32_t* win;             // angle windows lo[D], hi[D]
 };
 
+// Through-point restriction: vertex x_j equals x (j = -1: none).
+struct Pin {
+    int j = -1;
+    int x = 0;
+};
+
 size_t dp_plane_bytes(const Geometry& g);
 size_t dp_backptr_bytes(const Geometry& g, bool a16);
 size_t dp_key_count(const Geometry& g);
 hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
-                     const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream);
+                     const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream,
+                     Pin pin = Pin{});
 
 // One image's DP, argmax and walk.
 struct DpJobSpec {
@@ -72,8 +79,17 @@ struct DpJobSpec {
     DpBuffers buf;
     int32_t* score;
     int32_t* xs;
+    Pin pin;
 };
 // Several images; images of one window class share every step launch.
 hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t stream);
+
+// ---- optional input steps ---------------------------------------------------
+// Detection image from the input: transposed when `transpose` (mostly
+// horizontal curves), then each of its rows smoothed with the binomial kernel
+// of radius `radius` (0: copy).  Input [h][w]; output [w][h] when transposed,
+// else [h][w]; same pixel type.
+hipError_t launch_prep(const void* img, int dtype, int h, int w, int radius, int transpose,
+                       void* out, hipStream_t stream);
 
 }  // namespace fhtp

@@ -28,12 +28,14 @@ ERR_HIP = -6
 ERR_UNSUPPORTED = -7
 ERR_DTYPE = -8
 ERR_POINT = -9
+ERR_OPTION = -10
 
 EXPORTED = (
     "fhtp_strerror", "fhtp_last_error_detail", "fhtp_version", "fhtp_table_shape",
     "fhtp_fht_workspace_bytes", "fhtp_fht_bands", "fhtp_dp_workspace_bytes", "fhtp_polyline_dp",
     "fhtp_detect_workspace_bytes", "fhtp_detect_polyline", "fhtp_batch_workspace_bytes",
-    "fhtp_detect_batch",
+    "fhtp_detect_batch", "fhtp_detect_ex_workspace_bytes", "fhtp_detect_polyline_ex",
+    "fhtp_prepare_image",
 )
 
 
@@ -57,6 +59,19 @@ class Job(C.Structure):
 
     _fields_ = [("img", C.c_void_p), ("dtype", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
                 ("k", C.c_int32), ("bend", Bend), ("score", C.c_void_p), ("xs", C.c_void_p)]
+
+
+class Options(C.Structure):
+    """fhtp_options: smoothing radius, orientation and the through-point pin."""
+
+    _fields_ = [("smooth_radius", C.c_int32), ("horizontal", C.c_int32),
+                ("pin_boundary", C.c_int32), ("pin_pos", C.c_int32)]
+
+
+def make_options(smooth_radius: int = 0, horizontal: bool = False, pin=None) -> Options:
+    """pin = (band boundary j, column or row) or None."""
+    pj, pp = (-1, 0) if pin is None else (int(pin[0]), int(pin[1]))
+    return Options(int(smooth_radius), int(bool(horizontal)), pj, pp)
 
 
 def make_bend(bend: Optional[int] = None, gamma: Optional[float] = None) -> Bend:
@@ -94,6 +109,10 @@ def lib() -> C.CDLL:
     L.fhtp_detect_polyline.argtypes = [vp, i32, i32, i32, i32, Bend, vp, sz, vp, vp, vp]
     L.fhtp_batch_workspace_bytes.argtypes = [C.POINTER(Job), i32, szp]
     L.fhtp_detect_batch.argtypes = [C.POINTER(Job), i32, vp, sz, vp]
+    optp = C.POINTER(Options)
+    L.fhtp_detect_ex_workspace_bytes.argtypes = [i32, i32, i32, i32, Bend, optp, szp]
+    L.fhtp_detect_polyline_ex.argtypes = [vp, i32, i32, i32, i32, Bend, optp, vp, sz, vp, vp, vp]
+    L.fhtp_prepare_image.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
     for name in EXPORTED:
         if name not in ("fhtp_strerror", "fhtp_last_error_detail", "fhtp_version"):
             getattr(L, name).restype = C.c_int
@@ -139,6 +158,16 @@ def detect_workspace_bytes(dtype: int, h: int, w: int, k: int, bend: Bend) -> in
     out = C.c_size_t()
     _check(lib().fhtp_detect_workspace_bytes(dtype, h, w, k, bend, C.byref(out)),
            "detect_workspace_bytes")
+    return out.value
+
+
+def detect_ex_workspace_bytes(dtype: int, h: int, w: int, k: int, bend: Bend,
+                              opt: Optional[Options]) -> int:
+    out = C.c_size_t()
+    _check(lib().fhtp_detect_ex_workspace_bytes(dtype, h, w, k, bend,
+                                                None if opt is None else C.byref(opt),
+                                                C.byref(out)),
+           "detect_ex_workspace_bytes")
     return out.value
 
 
@@ -231,6 +260,45 @@ def detect_polyline(img, k: int, bend: Optional[int] = None, gamma: Optional[flo
     rc = lib().fhtp_detect_polyline(img.data_ptr(), dt, h, w, k, b, _ptr(ws_t), ws_n,
                                     score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
     _check(rc, "detect_polyline")
+    return score, xs
+
+
+def prepare_image(img, smooth_radius: int = 0, horizontal: bool = False, out=None, stream=None):
+    """Detection image of a device image: transposed if horizontal, rows smoothed."""
+    torch = _torch()
+    _require_device(img, "img")
+    h, w = img.shape
+    shape = (w, h) if horizontal else (h, w)
+    if out is None:
+        out = torch.empty(shape, dtype=img.dtype, device=img.device)
+    rc = lib().fhtp_prepare_image(img.data_ptr(), _dtype_code(img), h, w, int(smooth_radius),
+                                  int(bool(horizontal)), out.data_ptr(), _stream_ptr(stream))
+    _check(rc, "prepare_image")
+    return out
+
+
+def detect_polyline_ex(img, k: int, bend: Optional[int] = None, gamma: Optional[float] = None,
+                       smooth_radius: int = 0, horizontal: bool = False, pin=None, ws=None,
+                       score=None, xs=None, stream=None):
+    """The detector with row smoothing, orientation and a through-point pin.
+
+    pin = (band boundary j, position) or None; positions and the returned xs
+    are rows instead of columns when horizontal.
+    """
+    torch = _torch()
+    _require_device(img, "img")
+    h, w = img.shape
+    dt = _dtype_code(img)
+    b = make_bend(bend, gamma)
+    opt = make_options(smooth_radius, horizontal, pin)
+    if score is None:
+        score = torch.empty(1, dtype=torch.int32, device=img.device)
+    if xs is None:
+        xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
+    ws_t, ws_n = _ws(detect_ex_workspace_bytes(dt, h, w, k, b, opt), img.device, ws)
+    rc = lib().fhtp_detect_polyline_ex(img.data_ptr(), dt, h, w, k, b, C.byref(opt), _ptr(ws_t),
+                                       ws_n, score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
+    _check(rc, "detect_polyline_ex")
     return score, xs
 
 

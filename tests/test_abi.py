@@ -12,6 +12,7 @@ import re
 import numpy as np
 import pytest
 
+import oracle
 from paper_1912_01884_amd import fhtp
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -174,3 +175,55 @@ def test_batch_rejects_any_invalid_job_before_launch():
     arr = (fhtp.Job * 1)(good)
     assert L.fhtp_detect_batch(arr, 1, C.c_void_p(256), 16, None) == fhtp.ERR_WORKSPACE
     assert L.fhtp_detect_batch(arr, 1, None, 1 << 30, None) == fhtp.ERR_NULL
+
+
+def test_detect_ex_validation_matches_oracle(orc):
+    """Option and point errors agree with the oracle's, and nothing is launched."""
+    L = fhtp.lib()
+    b = fhtp.make_bend(1)
+    dummy = C.c_void_p(256)
+    img = np.zeros((16, 32), np.uint8)
+    cases = [
+        (dict(smooth_radius=8), fhtp.ERR_OPTION),
+        (dict(smooth_radius=-1), fhtp.ERR_OPTION),
+        (dict(pin=(5, 0)), fhtp.ERR_POINT),
+        (dict(pin=(1, 32)), fhtp.ERR_POINT),
+        (dict(pin=(1, -1)), fhtp.ERR_POINT),
+        (dict(horizontal=True, pin=(2, 16)), fhtp.ERR_POINT),
+    ]
+    for kw, code in cases:
+        with pytest.raises(oracle.OracleError) as e:
+            orc.detect_ex(img, 4, bend=1, **kw)
+        assert e.value.code == code, kw
+        opt = fhtp.make_options(**kw)
+        out = C.c_size_t()
+        assert L.fhtp_detect_ex_workspace_bytes(0, 16, 32, 4, b, C.byref(opt), C.byref(out)) == code
+        assert L.fhtp_detect_polyline_ex(dummy, 0, 16, 32, 4, b, C.byref(opt), dummy, 1 << 40,
+                                         dummy, dummy, None) == code
+    bad = fhtp.Options(0, 2, -1, 0)
+    out = C.c_size_t()
+    assert L.fhtp_detect_ex_workspace_bytes(0, 16, 32, 4, b, C.byref(bad), C.byref(out)) == \
+        fhtp.ERR_OPTION
+    # horizontal: k must split the 32 columns into power-of-two strips
+    opt = fhtp.make_options(horizontal=True)
+    assert L.fhtp_detect_ex_workspace_bytes(0, 16, 32, 3, b, C.byref(opt), C.byref(out)) == \
+        fhtp.ERR_DIMS
+    assert L.fhtp_detect_ex_workspace_bytes(0, 16, 32, 4, b, C.byref(opt), C.byref(out)) == 0
+    # the overflow bound applies to the rows of the detection image
+    assert L.fhtp_detect_ex_workspace_bytes(1, 4, 65536, 65536, b, C.byref(opt),
+                                            C.byref(out)) == fhtp.ERR_OVERFLOW
+    assert L.fhtp_detect_polyline_ex(None, 0, 16, 32, 4, b, None, dummy, 1 << 40, dummy, dummy,
+                                     None) == fhtp.ERR_NULL
+    assert L.fhtp_detect_polyline_ex(dummy, 0, 16, 32, 4, b, C.byref(opt), dummy, 1, dummy,
+                                     dummy, None) == fhtp.ERR_WORKSPACE
+
+
+def test_detect_ex_workspace_sizes():
+    b = fhtp.make_bend(2)
+    plain = fhtp.detect_workspace_bytes(0, 256, 300, 4, b)
+    assert fhtp.detect_ex_workspace_bytes(0, 256, 300, 4, b, None) == plain
+    assert fhtp.detect_ex_workspace_bytes(0, 256, 300, 4, b, fhtp.make_options(pin=(2, 7))) == plain
+    sm = fhtp.detect_ex_workspace_bytes(0, 256, 300, 4, b, fhtp.make_options(smooth_radius=2))
+    assert sm == plain + (256 * 300 + 255) // 256 * 256
+    hz = fhtp.detect_ex_workspace_bytes(1, 300, 256, 4, b, fhtp.make_options(horizontal=True))
+    assert hz == fhtp.detect_workspace_bytes(1, 256, 300, 4, b) + (2 * 256 * 300 + 255) // 256 * 256
