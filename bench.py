@@ -119,6 +119,61 @@ def mixed_batch(n_images, reps, dev, stream):
             "batched_mpix_per_s": round(mpix / (ms_batch * 1e-3), 1)}
 
 
+def serving(dev, rates, count, streams=4, max_batch=64):
+    """Open-loop Poisson arrivals of the mixed-size requests: continuous batching vs plain.
+
+    Requests are the 256 mixed-size images (device resident) in a seeded
+    random order; arrivals are a Poisson stream at each rate (and all at once
+    for the saturation run).  Latency is host-observed completion minus the
+    scheduled arrival.  The two servers must return identical results.
+    """
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1912_01884_amd import fhtp
+    from paper_1912_01884_amd.serve import (FhtpBackend, PlainServer, Request, Server,
+                                            poisson_arrivals, run_open_loop)
+
+    batch = synth.make_c4_batch(256)
+    imgs = [torch.from_numpy(s.image).to(dev) for s in batch]
+    pick = np.random.default_rng([191201884, 5, 998]).integers(0, len(batch), size=count)
+    scores = torch.zeros((2, count), dtype=torch.int32, device=dev)
+    xss = torch.zeros((2, count, 17), dtype=torch.int32, device=dev)
+    max_bytes = max(fhtp.detect_workspace_bytes(s.dtype_code, s.h, s.w, s.k, fhtp.make_bend(s.bend))
+                    for s in batch)
+    backend = FhtpBackend(dev, arena_bytes=8 << 30, streams=streams)
+    plain = PlainServer(dev, max_request_bytes=max_bytes)
+    torch.cuda.synchronize()
+
+    def requests(which):
+        out = []
+        for i, q in enumerate(pick):
+            s = batch[q]
+            out.append(Request(img=imgs[q], k=s.k, bend=s.bend, score=scores[which, i:i + 1],
+                               xs=xss[which, i, :s.k + 1], rid=i))
+        return out
+
+    res = {}
+    for rate in rates:
+        arr = poisson_arrivals(rate, count, [191201884, 5, 999])
+        srv = Server(backend, streams=streams, max_batch=max_batch)
+        a = run_open_loop(srv, requests(0), arr, timeout=300)
+        a["groups"] = srv.groups_launched
+        b = run_open_loop(plain, requests(1), arr, timeout=300)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(scores[0], scores[1]) and torch.equal(xss[0], xss[1]))
+        key = "saturation" if rate == float("inf") else f"{int(rate)}_per_s"
+        res[key] = {"server": a, "plain": b, "identical_results": same,
+                    "throughput_ratio": round(a["images_per_s"] / b["images_per_s"], 2)}
+        scores.zero_()
+        xss.zero_()
+    res["requests_per_rate"] = count
+    res["streams"] = streams
+    res["max_group"] = max_batch
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +185,10 @@ def main():
     ap.add_argument("--batch-images", type=int, default=256,
                     help="images of the mixed-size workload timed batched vs one at a time "
                          "(0 skips it)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per arrival rate in the serving run (0 skips it)")
+    ap.add_argument("--serve-rates", default="200,1000,5000,inf",
+                    help="Poisson arrival rates (requests/s) of the serving run; inf = all at once")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -195,7 +254,7 @@ def main():
     model = byte_model(h, w, k, bpp)
     fht_gbps = model["fht_kernel"] / (ms_fht * 1e-3) / 1e9
     line = {
-        "metric": "FHT+DP Mpix/s @4096x4096,k=32 (HBM GB/s beside it)",
+        "metric": "FHT+DP Mpix/s & HBM GB/s @4096\u00b2,k=32; batched imgs/s vs plain; p99 ms",
         "value": round(h * w / (ms_per_step * 1e-3) / 1e6, 2),
         "unit": "Mpix/s",
         "n_gpus": 1,
@@ -223,6 +282,12 @@ def main():
     }
     if args.batch_images > 0:
         line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream)
+    if args.serve_requests > 0:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        line["serving"] = serving(dev, rates, args.serve_requests)
+        k1000 = line["serving"].get("1000_per_s")
+        if k1000:
+            line["p99_ms"] = k1000["server"]["p99_ms"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s.image, k, B, args.cpu_seconds)
     res = (int(score.cpu()[0]), xs.cpu().numpy().tolist())
