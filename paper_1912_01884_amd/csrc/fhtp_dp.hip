@@ -220,28 +220,45 @@ __device__ __forceinline__ void finish(const DpJob& a, unsigned long long best, 
     }
 }
 
-// One workgroup of a mode-0 step with the window [d - B, d + B] fixed at
-// compile time: all loads first (the window column of V_{i+1} and the H_i
-// cells), then the sliding maximum with its argmax, then the cells.
-template <int B, int DC, typename AT>
-__device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx, int by) {
+// Buffer view of rows [row0, row0 + rows) of a plane (pitch elements of esz
+// bytes per row), clamped to the plane's rows [0, D).  row0 is wave-uniform,
+// so the descriptor lives in scalar registers and every access is a 32-bit
+// offset from it: no 64-bit address arithmetic per load, which would tie
+// later address computations to registers of loads still in flight.
+struct RowView {
+    __amdgpu_buffer_rsrc_t rs;
+    int base;  // plane row at byte offset 0
+    int end;   // one past the last row covered
+};
+
+__device__ __forceinline__ RowView row_view(const void* plane, int pitch, int esz, int row0,
+                                            int rows, int D) {
+    RowView v;
+    v.base = min(max(row0, 0), D - 1);
+    v.end = min(row0 + rows, D);
+    const int cnt = max(v.end - v.base, 1);
+    v.rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(static_cast<const char*>(plane)) + (size_t)v.base * pitch * esz,
+        (short)0, cnt * pitch * esz, 0x00020000);
+    return v;
+}
+
+// Byte offset of a row inside the view (0 for rows it does not cover, whose
+// lanes are masked by an out-of-range lane offset instead).
+__device__ __forceinline__ unsigned int row_off(const RowView& v, int row, int pitch, int esz) {
+    return (row >= v.base && row < v.end) ? (unsigned int)(row - v.base) * pitch * esz : 0u;
+}
+
+constexpr unsigned int kOut = 0x80000000u;  // lane offset past every view: loads 0, stores drop
+
+// Sliding maximum of the windows [j, j + 2B] of v, j = 0 .. DC-1, with the
+// smallest index reaching it (van Herk / Gil-Werman: suffix maxima and prefix
+// maxima inside blocks of the window length).
+template <int B, int DC>
+__device__ __forceinline__ void window_max(const int (&v)[DC + 2 * B], int (&m)[DC],
+                                           int (&ia)[DC]) {
     constexpr int L = 2 * B + 1;
     constexpr int NV = DC + 2 * B;
-    const int n = a.n, w = a.w;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xp = bx * 64 + lane;
-    const int chunk = by * kWaves + wave;
-    const int d0 = -(n - 1) + chunk * DC;
-
-    int hv[DC];
-#pragma unroll
-    for (int j = 0; j < DC; ++j) hv[j] = load_h(a, xp, d0 + j);
-    const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
-    int v[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = load_v(a.vin, a.vin_pitch, xp, d0 - B + j, n, mk);
-
-    // Suffix maxima inside window-length blocks (smallest index on ties).
     int sv[NV], si[NV];
 #pragma unroll
     for (int q = NV - 1; q >= 0; --q) {
@@ -254,7 +271,6 @@ __device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx,
             si[q] = take ? q : si[q + 1];
         }
     }
-    unsigned long long best = 0;
     int pv = 0, pi = 0;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -268,13 +284,167 @@ __device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx,
         if (q >= 2 * B) {
             const int j = q - 2 * B;  // window [j, q]: suffix of j's block + prefix of q's block
             const bool s_wins = sv[j] >= pv;
-            const int m = s_wins ? sv[j] : pv;
-            const int ia = s_wins ? si[j] : pi;
-            const int ra = chunk * DC - B + ia;  // row of d' = d0 - B + ia
-            emit<AT>(a, m, ra, hv[j], xp, d0 + j, best);
+            m[j] = s_wins ? sv[j] : pv;
+            ia[j] = s_wins ? si[j] : pi;
+        }
+    }
+}
+
+// A wave whose every cell, window row and successor column lies inside the
+// image and the planes (and no pin applies) needs no masks: one descriptor
+// per plane, one lane offset per access pattern, rows as scalar offsets.
+template <int B, int DC>
+__device__ __forceinline__ bool wave_is_interior(const DpJob& a, int X0, int r0, int d0) {
+    const int D = 2 * a.n - 1, w = a.w;
+    return a.vin_pin == 0 && a.out_pin_x < 0 && r0 - B >= 0 && r0 + DC + B <= D &&
+           X0 + 64 <= w &&
+           X0 + d0 - B >= 0 && X0 + 63 + d0 + DC - 1 + B < w &&  // x' + d' for every window row
+           X0 - (d0 + DC - 1) >= 0 && X0 + 63 - d0 < w;          // x = x' - d for every cell
+}
+
+template <int B, int DC, typename AT>
+__device__ __forceinline__ unsigned long long fixed_interior(const DpJob& a, int X0, int r0,
+                                                             int d0) {
+    constexpr int NV = DC + 2 * B;
+    const int D = 2 * a.n - 1;
+    const int xp = X0 + (int)(threadIdx.x & 63);
+    const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
+    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
+    const __amdgpu_buffer_rsrc_t vr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t*>(a.vin) + (size_t)(r0 - B) * a.vin_pitch, (short)0, (int)(NV * vp),
+        0x00020000);
+    const __amdgpu_buffer_rsrc_t hr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t*>(a.htab) + (size_t)r0 * a.h_pitch, (short)0, (int)(DC * hp),
+        0x00020000);
+    // cell j sits at column x' - d0 - j: one lane offset for the row group,
+    // the column step as a constant
+    const unsigned int diag = (unsigned int)(xp - d0 - (DC - 1)) * 4u;
+    int hv[DC], v[NV];
+#pragma unroll
+    for (int j = 0; j < DC; ++j)
+        hv[j] = __builtin_amdgcn_raw_buffer_load_b32(hr, (int)(diag + (DC - 1 - j) * 4),
+                                                     (int)(j * hp), 0);
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = __builtin_amdgcn_raw_buffer_load_b32(vr, xp * 4, (int)(j * vp), 0);
+    __builtin_amdgcn_sched_barrier(0);
+    int m[DC], ia[DC];
+    window_max<B, DC>(v, m, ia);
+    unsigned long long best = 0;
+    if (a.key) {
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+            const int val = m[j] >= 0 ? hv[j] + m[j] : -1;
+            const unsigned long long kk = pack_key(val, xp - d0 - j, r0 + j, D);
+            best = kk > best ? kk : best;
+        }
+        return best;
+    }
+    const unsigned int op = (unsigned int)a.v_pitch * 4u;
+    const unsigned int ap = (unsigned int)a.a_pitch * sizeof(AT);
+    const __amdgpu_buffer_rsrc_t orr = __builtin_amdgcn_make_buffer_rsrc(
+        a.vout + (size_t)r0 * a.v_pitch, (short)0, (int)(DC * op), 0x00020000);
+    const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+        static_cast<AT*>(a.aout) + (size_t)r0 * a.a_pitch, (short)0, (int)(DC * ap), 0x00020000);
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const int val = m[j] >= 0 ? hv[j] + m[j] : -1;
+        const unsigned int row = (unsigned int)(r0 - B + ia[j]);  // d' + n - 1 of the maximum
+        if constexpr (sizeof(AT) == 1)
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)row, ar, xp, (int)(j * ap), 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)row, ar, xp * 2, (int)(j * ap), 0);
+        __builtin_amdgcn_raw_buffer_store_b32(val, orr, (int)(diag + (DC - 1 - j) * 4),
+                                              (int)(j * op), 0);
+    }
+    return best;
+}
+
+// One wave of a mode-0 step with the window [d - B, d + B] fixed at compile
+// time, anywhere in the planes: every access masked (cells outside the image
+// or the planes, pinned columns).  All loads first (the window column of
+// V_{i+1} and the H_i cells), then the sliding maximum, then the cells.
+template <int B, int DC, typename AT>
+__device__ __forceinline__ unsigned long long fixed_general(const DpJob& a, int X0, int r0,
+                                                            int d0) {
+    constexpr int NV = DC + 2 * B;
+    const int n = a.n, w = a.w;
+    const int D = 2 * n - 1;
+    const int xp = X0 + (int)(threadIdx.x & 63);
+    const bool col_ok = (unsigned)xp < (unsigned)w;
+
+    // H_i(x' - d, d), d = d0 + j: rows r0 + j, column x' - d.
+    const RowView hview = row_view(a.htab, a.h_pitch, 4, r0, DC, D);
+    int hv[DC];
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const int x = xp - d0 - j;
+        const bool ok = col_ok && r0 + j < D && (unsigned)x < (unsigned)w;
+        const int t = __builtin_amdgcn_raw_buffer_load_b32(
+            hview.rs, (int)(ok ? (unsigned int)x * 4u : kOut),
+            (int)row_off(hview, r0 + j, a.h_pitch, 4), 0);
+        hv[j] = ok ? t : 0;
+    }
+    // V_{i+1}(x', d'), d' = d0 - B + j: rows r0 - B + j, column x'.
+    const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
+    const bool xin = (unsigned)(xp - mk.xlo) < (unsigned)mk.xlen;
+    const int tx = xp + d0 - B - mk.tlo;  // x' + d' - tlo at j = 0
+    const RowView vview = row_view(a.vin, a.vin_pitch, 4, r0 - B, NV, D);
+    int v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int row = r0 - B + j;
+        const bool ok = xin && row >= 0 && row < D && (unsigned)(tx + j) < (unsigned)mk.tlen;
+        const int t = __builtin_amdgcn_raw_buffer_load_b32(
+            vview.rs, (int)(ok ? (unsigned int)xp * 4u : kOut),
+            (int)row_off(vview, row, a.vin_pitch, 4), 0);
+        v[j] = ok ? t : -1;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    int m[DC], ia[DC];
+    window_max<B, DC>(v, m, ia);
+
+    const bool last = a.key != nullptr;
+    const RowView aview = row_view(last ? a.vin : a.aout, a.a_pitch, sizeof(AT), r0, DC, D);
+    const RowView oview = row_view(last ? a.vin : a.vout, a.v_pitch, 4, r0, DC, D);
+    unsigned long long best = 0;
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const int ra = r0 - B + ia[j];  // row of the maximum's d'
+        const int r = r0 + j;
+        const int x = xp - d0 - j;
+        const bool cell = col_ok && r < D;
+        const bool live = cell && (unsigned)x < (unsigned)w;
+        const int val = (m[j] >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hv[j] + m[j] : -1;
+        if (last) {
+            const unsigned long long kk = live ? pack_key(val, x, r, D) : 0ull;
+            best = kk > best ? kk : best;
+        } else {
+            const unsigned int ar = row_off(aview, r, a.a_pitch, sizeof(AT));
+            const unsigned int vr = row_off(oview, r, a.v_pitch, 4);
+            const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
+            if constexpr (sizeof(AT) == 1)
+                __builtin_amdgcn_raw_buffer_store_b8(
+                    (unsigned char)av, aview.rs, (int)(cell ? (unsigned int)xp : kOut), (int)ar, 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b16(
+                    (unsigned short)av, aview.rs, (int)(cell ? (unsigned int)xp * 2u : kOut),
+                    (int)ar, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(
+                val, oview.rs, (int)(live ? (unsigned int)x * 4u : kOut), (int)vr, 0);
         }
     }
     return best;
+}
+
+template <int B, int DC, typename AT>
+__device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx, int by) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int X0 = bx * 64;
+    const int r0 = (by * kWaves + wave) * DC;  // table row of this wave's first displacement
+    const int d0 = r0 - (a.n - 1);
+    if (wave_is_interior<B, DC>(a, X0, r0, d0)) return fixed_interior<B, DC, AT>(a, X0, r0, d0);
+    return fixed_general<B, DC, AT>(a, X0, r0, d0);
 }
 
 // Step with the mode-0 window fixed at compile time.
