@@ -24,6 +24,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 
+# HBM bytes per launch of the band FHT kernel on the 4096x4096 uint16 image
+# (k = 32), from two rocprofv3 --pmc runs of `bench.py --probe` (FETCH_SIZE,
+# then WRITE_SIZE), each scaled by what the same counter reads for a copy of a
+# known size in the same run.  Valid only for the kernel source they were
+# taken on (sha256 of csrc/fhtp_fht.hip); otherwise the traffic is unknown.
+FHT_TRAFFIC = None
+
 
 def byte_model(h, w, k, bpp):
     """Algorithmic HBM bytes of one detection with materialised band tables."""
@@ -174,6 +181,38 @@ def serving(dev, rates, count, streams=4, max_batch=64):
     return res
 
 
+def fht_traffic():
+    import hashlib
+    if FHT_TRAFFIC is None:
+        return None
+    src = os.path.join(ROOT, "paper_1912_01884_amd", "csrc", "fhtp_fht.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != FHT_TRAFFIC["source_sha256"]:
+        return None
+    return FHT_TRAFFIC["fetch_bytes"] + FHT_TRAFFIC["write_bytes"]
+
+
+def probe(dev):
+    """A short program for hardware-counter runs: a 256 MiB fill and copy of known
+    size (counter calibration), then one band FHT and one DP of the 4096x4096 image."""
+    import torch
+
+    import synth
+    from paper_1912_01884_amd import fhtp
+
+    s = synth.make_c3()
+    img = torch.from_numpy(s.image).to(dev)
+    a = torch.empty(64 << 20, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    a.fill_(1)
+    b.copy_(a)
+    tables = fhtp.fht_bands(img, s.k)
+    score, xs = fhtp.polyline_dp(tables, s.h, s.w, s.k, bend=s.bend)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy 268435456 bytes; fht_bands + polyline_dp 4096x4096 k=32",
+                      "score": int(score.cpu()[0])}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +228,8 @@ def main():
                     help="requests per arrival rate in the serving run (0 skips it)")
     ap.add_argument("--serve-rates", default="200,1000,5000,inf",
                     help="Poisson arrival rates (requests/s) of the serving run; inf = all at once")
+    ap.add_argument("--probe", action="store_true",
+                    help="run the short counter-calibration program instead of the benchmark")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -202,6 +243,10 @@ def main():
 
     import synth
     from paper_1912_01884_amd import fhtp
+
+    if args.probe:
+        probe(torch.device("cuda:0"))
+        return
 
     s = synth.make_config(args.config)
     h, w, k, B = s.h, s.w, s.k, s.bend
@@ -253,6 +298,17 @@ def main():
 
     model = byte_model(h, w, k, bpp)
     fht_gbps = model["fht_kernel"] / (ms_fht * 1e-3) / 1e9
+    # One DP step launch moves H_i (columns < w), V_{i+1} and V_i (4 bytes a
+    # cell each) and A_{i+1} (1 or 2 bytes a cell).  The phase time includes
+    # the backtrace walk, so this per-step figure is a lower bound.
+    D = 2 * (h // k) - 1
+    step_bytes = D * w * (12 + (1 if D <= 256 else 2))
+    dp_gbps = step_bytes * max(k - 1, 1) / (ms_dp * 1e-3) / 1e9
+    dp_roofline = {"bound": "hbm", "kernel": "dp_step_fixed (31 launches + walk)",
+                   "achieved": round(dp_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                   "frac": round(dp_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                   "algorithmic_bytes_per_launch": step_bytes,
+                   "us_per_step_incl_walk": round(ms_dp * 1e3 / max(k - 1, 1), 3)}
     line = {
         "metric": "FHT+DP Mpix/s & HBM GB/s @4096\u00b2,k=32; batched imgs/s vs plain; p99 ms",
         "value": round(h * w / (ms_per_step * 1e-3) / 1e6, 2),
@@ -278,7 +334,10 @@ def main():
         "phase_ms": {"fht_bands": round(ms_fht, 4), "polyline_dp": round(ms_dp, 4)},
         "roofline": {"bound": "hbm", "kernel": "fht_reg_kernel",
                      "achieved": round(fht_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(fht_gbps / HBM_PEAK_GBPS, 4), "traffic": None},
+                     "frac": round(fht_gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": fht_traffic() if (h, w, k, bpp) == (4096, 4096, 32, 2) else None,
+                     "algorithmic_bytes": model["fht_kernel"]},
+        "roofline_dp_step": dp_roofline,
     }
     if args.batch_images > 0:
         line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream)

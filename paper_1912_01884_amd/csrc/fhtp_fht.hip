@@ -161,6 +161,7 @@ struct FhtJob {
 };
 
 constexpr int kPack = 32;  // runs per launch (kernel-argument size)
+constexpr int kXcds = 8;   // accelerator dies of the MI355X, each with its own L2
 
 // CAP runs per launch: 1 for a single image (small kernel arguments), kPack for batches.
 template <int CAP>
@@ -184,13 +185,19 @@ struct FhtItem {
     bool inside;
 };
 
+// Items of a row block alternate between the two directions, right-leaning
+// tiles left to right and left-leaning tiles (whose c-space runs right to
+// left in the image) in reverse, so consecutive items read overlapping image
+// columns: right tile t and left tile tiles-1-t share most of their pixels.
 template <int NDIR>
 __device__ __forceinline__ FhtItem fht_decode(const FhtJob& J, int local, int tid) {
     FhtItem it;
-    const int tile = local % J.tiles;
-    const int bd = local / J.tiles;  // blk * NDIR + dir
-    it.blk = bd / NDIR;
-    it.dir = bd % NDIR;
+    const int per_blk = NDIR * J.tiles;
+    it.blk = local / per_blk;
+    const int u = local - it.blk * per_blk;
+    it.dir = NDIR == 2 ? (u & 1) : 0;
+    const int t = NDIR == 2 ? (u >> 1) : u;
+    const int tile = it.dir ? J.tiles - 1 - t : t;
     it.c = tile * J.T + tid;
     const int cm = it.c % J.W;
     it.ximg = it.dir == 0 ? cm : (J.W - 1 - cm);
@@ -288,7 +295,14 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
     const int total = pk.total;
 
     uint32_t pre[C::NPK];
+    // Workgroups are spread over the XCDs round-robin (workgroup b on XCD
+    // b % 8).  When the grid covers every item, give each XCD a contiguous run
+    // of items instead, so the tiles that share pixel columns meet in one L2.
     int item = blockIdx.x;
+    if ((int)gridDim.x == total) {
+        const int xcd = item % kXcds, slot = item / kXcds;
+        item = xcd * (total / kXcds) + min(xcd, total % kXcds) + slot;
+    }
     if constexpr (C::PREFETCH) {
         const int j = fht_find_job(pk, item);
         fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[j], item - pk.job[j].item0, tid, pre);
