@@ -15,7 +15,7 @@ from tests.gpu_util import announce, host, require_gpu, to_device
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg", ["C1", "C2"])
+@pytest.mark.parametrize("cfg", ["C1", "C2", "C3"])
 def test_graph_replays_match_eager(cfg):
     from paper_1912_01884_amd import fhtp
     dev = require_gpu()
