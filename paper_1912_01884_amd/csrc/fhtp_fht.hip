@@ -355,6 +355,18 @@ struct CombinePack {
 
 constexpr int kShiftGroup = 16;
 
+// dyadic_offset(7 + SH, s, m << 7): only the bits of m are set in the row, and
+// bit b of m is row bit 7 + b, i.e. j = SH - 1 - b of the closed form.  Every
+// shift is a constant, so the offsets cost a handful of scalar operations.
+template <int SH>
+__device__ __forceinline__ int sub_block_offset(int s, int m) {
+    int off = 0;
+#pragma unroll
+    for (int b = 0; b < SH; ++b)
+        if ((m >> b) & 1) off += (s >> (SH - b)) + ((s >> (SH - 1 - b)) & 1);
+    return off;
+}
+
 template <int SH>  // SH = p - 7, M = 2^SH sub-blocks per band
 __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
     constexpr int M = 1 << SH;
@@ -387,7 +399,7 @@ __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
         int32_t acc = 0;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            int cc = c + dyadic_offset(p, s, m << kRegMaxP);
+            int cc = c + sub_block_offset<SH>(s, m);
             cc -= cc >= W ? W : 0;  // offsets are below n < W, so one wrap at most
             acc += base[((size_t)(m * 2 + dir) * (1 << kRegMaxP) + sf) * row + cc];
         }
