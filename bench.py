@@ -127,7 +127,7 @@ def mixed_batch(n_images, reps, dev, stream):
             "batched_mpix_per_s": round(mpix / (ms_batch * 1e-3), 1)}
 
 
-def serving(dev, rates, count, streams=4, max_batch=64):
+def serving(dev, rates, count, streams=4, max_batch=256):
     """Open-loop Poisson arrivals of the mixed-size requests: continuous batching vs plain.
 
     Requests are the 256 mixed-size images (device resident) in a seeded

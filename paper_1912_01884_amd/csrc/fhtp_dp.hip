@@ -48,7 +48,7 @@ namespace {
 constexpr int kWaves = 4;      // waves per workgroup, one displacement chunk each
 constexpr int kMaxFixedB = 16; // largest bend bound with a register-window kernel
 constexpr int kDCGeneric = 16; // displacements per thread in the scanning kernels
-constexpr int kPack = 32;      // images per launch (kernel-argument size)
+constexpr int kPack = 256;     // images per launch (kernel arguments of up to 32 KB)
 
 // One image in one step launch.
 struct DpJob {
@@ -101,10 +101,19 @@ struct WalkPack {
 
 template <int CAP>
 __device__ __forceinline__ int dp_find_job(const DpPack<CAP>& pk, int item) {
-    int j = 0;
-    if constexpr (CAP > 1)
-        for (int q = 1; q < pk.count; ++q) j = item >= pk.job[q].item0 ? q : j;
-    return j;
+    // the last job whose first item is <= item (item0 ascends): binary search
+    int lo = 0;
+    if constexpr (CAP > 1) {
+        int hi = pk.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pk.job[mid].item0 <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+    }
+    return lo;
 }
 
 __device__ __forceinline__ unsigned long long pack_key(int val, int x, int r, int D) {

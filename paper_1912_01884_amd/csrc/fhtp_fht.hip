@@ -160,7 +160,7 @@ struct FhtJob {
     int to_table;     // 1: band tables; 0: c-space sub-block scratch
 };
 
-constexpr int kPack = 32;  // runs per launch (kernel-argument size)
+constexpr int kPack = 256;  // runs per launch (kernel arguments of up to 32 KB)
 constexpr int kXcds = 8;   // accelerator dies of the MI355X, each with its own L2
 
 // CAP runs per launch: 1 for a single image (small kernel arguments), kPack for batches.
@@ -174,10 +174,19 @@ struct FhtPack {
 // The run a work item belongs to (uniform across the workgroup).
 template <int CAP>
 __device__ __forceinline__ int fht_find_job(const FhtPack<CAP>& pk, int item) {
-    int j = 0;
-    if constexpr (CAP > 1)
-        for (int q = 1; q < pk.count; ++q) j = item >= pk.job[q].item0 ? q : j;
-    return j;
+    // the last job whose first item is <= item (item0 ascends): binary search
+    int lo = 0;
+    if constexpr (CAP > 1) {
+        int hi = pk.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pk.job[mid].item0 <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+    }
+    return lo;
 }
 
 struct FhtItem {
@@ -372,7 +381,13 @@ __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
     constexpr int M = 1 << SH;
     const int item = blockIdx.x;
     int j = 0;
-    for (int q = 1; q < pk.count; ++q) j = item >= pk.job[q].item0 ? q : j;
+    for (int hi = pk.count - 1; j < hi;) {  // last job with item0 <= item
+        const int mid = (j + hi + 1) >> 1;
+        if (pk.job[mid].item0 <= item)
+            j = mid;
+        else
+            hi = mid - 1;
+    }
     const CombineJob& J = pk.job[j];
     const int p = J.p;
     const int n = 1 << p;

@@ -126,7 +126,7 @@ class _Group:
 class Server:
     """Continuous batching over a backend (see the module docstring)."""
 
-    def __init__(self, backend, streams: int = 4, max_batch: int = 64,
+    def __init__(self, backend, streams: int = 4, max_batch: int = 256,
                  clock: Callable[[], float] = time.perf_counter):
         if streams < 1 or max_batch < 1:
             raise ValueError("need at least one stream and a group size of at least one")
