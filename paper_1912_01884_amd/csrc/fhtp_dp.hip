@@ -468,51 +468,114 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
 }
 
 // Step with per-displacement windows [lo(d), hi(d)] (large mode-0 bounds, the
-// angle form, no bound at all), scanning each window.
+// angle form, no bound at all).  Both window ends are non-decreasing in d, so
+// the windows of a wave's kDCGeneric displacements fall into groups that
+// share a point c (c = hi of the group's first window): each window of a
+// group is [lo, c] + [c+1, hi].  One descending scan from c gives every
+// [lo, c] maximum (recorded as the scan passes each lo) and one ascending scan
+// from c+1 gives every [c+1, hi] maximum, so each V cell of the union of the
+// windows is read and compared once, with the loads issued sixteen at a time.
+// Ties keep the smallest d' (descending scans take equal values, ascending
+// ones only larger values, and the [lo, c] part wins ties).
+constexpr int kScanTile = 16;
+constexpr int kEmpty = -2147483647 - 1;  // no cell yet (below every V, -1 included)
+
 template <typename AT, int CAP>
 __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
+    __shared__ int res_v[kWaves][kDCGeneric][64];
+    __shared__ int res_i[kWaves][kDCGeneric][64];
     const int jj = dp_find_job(pk, blockIdx.x);
     const DpJob& a = pk.job[jj];
     const int local = blockIdx.x - a.item0;
     const int bx = local % a.items_x, by = local / a.items_x;
     const int n = a.n, w = a.w;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int xp = bx * 64 + lane;
     const int chunk = by * kWaves + wave;
     const int d0 = -(n - 1) + chunk * kDCGeneric;
     const int D = 2 * n - 1;
+    const int jn = min(kDCGeneric, D - (d0 + n - 1));  // displacements of this wave
     const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
-    unsigned long long best = 0;
-    if (a.full) {
-        // Section 2.2: every d shares the maximum of the whole successor column.
-        int m = load_v(a.vin, a.vin_pitch, xp, -(n - 1), n, mk);
-        int ia = -(n - 1);
-        for (int dp = -(n - 1) + 1; dp <= n - 1; ++dp) {
-            const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, mk);
-            if (vv > m) {
-                m = vv;
-                ia = dp;
-            }
-        }
-        for (int j = 0; j < kDCGeneric; ++j)
-            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d0 + j), xp, d0 + j, best);
-    } else {
-        for (int j = 0; j < kDCGeneric; ++j) {
-            const int d = d0 + j;
-            if (d + n - 1 >= D) break;
-            int lo, hi;
-            window_of(n, a.full, a.win, a.bound, d, lo, hi);
-            int m = load_v(a.vin, a.vin_pitch, xp, lo, n, mk);
-            int ia = lo;
-            for (int dp = lo + 1; dp <= hi; ++dp) {
-                const int vv = load_v(a.vin, a.vin_pitch, xp, dp, n, mk);
-                if (vv > m) {
-                    m = vv;
-                    ia = dp;
+    int hv[kDCGeneric];
+#pragma unroll
+    for (int j = 0; j < kDCGeneric; ++j) hv[j] = load_h(a, xp, d0 + j);
+    // The wave's windows, one per lane (lanes 0 .. kDCGeneric-1), read back as
+    // scalars with readlane: no memory access inside the scans.
+    int wlo = 0, whi = 0;
+    {
+        const int dl = d0 + min(lane, kDCGeneric - 1);
+        window_of(n, a.full, a.win, a.bound, min(dl, n - 1), wlo, whi);
+    }
+    auto lo_of = [&](int j) { return __builtin_amdgcn_readlane(wlo, j); };
+    auto hi_of = [&](int j) { return __builtin_amdgcn_readlane(whi, j); };
+    for (int ja = 0; ja < jn;) {
+        const int c = hi_of(ja);
+        int jb = ja;
+        while (jb + 1 < jn && lo_of(jb + 1) <= c) ++jb;
+        // [lo_j, c], descending; record at each lo_j (j = jb down to ja)
+        const int first = lo_of(ja);
+        int cv = kEmpty, ci = c;
+        int p = jb, plo = lo_of(jb);
+        for (int t0 = c; t0 >= first; t0 -= kScanTile) {
+            int v[kScanTile];
+#pragma unroll
+            for (int q = 0; q < kScanTile; ++q) v[q] = load_v(a.vin, a.vin_pitch, xp, t0 - q, n, mk);
+#pragma unroll
+            for (int q = 0; q < kScanTile; ++q) {
+                const int dp = t0 - q;
+                if (dp < first) break;
+                const bool take = v[q] >= cv;
+                cv = take ? v[q] : cv;
+                ci = take ? dp : ci;
+                while (p >= ja && plo == dp) {
+                    res_v[wave][p][lane] = cv;
+                    res_i[wave][p][lane] = ci;
+                    --p;
+                    plo = p >= ja ? lo_of(p) : kEmpty;
                 }
             }
-            emit<AT>(a, m, ia + n - 1, load_h(a, xp, d), xp, d, best);
         }
+        // [c+1, hi_j], ascending; record at each hi_j (j = ja up to jb)
+        const int last = hi_of(jb);
+        cv = kEmpty;
+        ci = c;
+        p = ja;
+        int phi = hi_of(ja);
+        auto record_up = [&](int at) {
+            while (p <= jb && phi == at) {
+                const int sv = res_v[wave][p][lane];
+                const bool up = cv > sv;  // the [lo, c] part wins ties
+                res_v[wave][p][lane] = up ? cv : sv;
+                if (up) res_i[wave][p][lane] = ci;
+                ++p;
+                phi = p <= jb ? hi_of(p) : kEmpty;
+            }
+        };
+        record_up(c);
+        for (int t0 = c + 1; t0 <= last; t0 += kScanTile) {
+            int v[kScanTile];
+#pragma unroll
+            for (int q = 0; q < kScanTile; ++q) v[q] = load_v(a.vin, a.vin_pitch, xp, t0 + q, n, mk);
+#pragma unroll
+            for (int q = 0; q < kScanTile; ++q) {
+                const int dp = t0 + q;
+                if (dp > last) break;
+                const bool take = v[q] > cv;
+                cv = take ? v[q] : cv;
+                ci = take ? dp : ci;
+                record_up(dp);
+            }
+        }
+        ja = jb + 1;
+    }
+    unsigned long long best = 0;
+#pragma unroll
+    for (int j = 0; j < kDCGeneric; ++j) {
+        if (j >= jn) break;
+        const int m = res_v[wave][j][lane];
+        const int ia = res_i[wave][j][lane];
+        emit<AT>(a, m, ia + n - 1, hv[j], xp, d0 + j, best);
     }
     finish(a, best, local);
 }
