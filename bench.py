@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -340,6 +341,21 @@ def main():
                      "algorithmic_bytes": model["fht_kernel"]},
         "roofline_dp_step": dp_roofline,
     }
+    # The DP under the other bend forms on the same tables: the angle bound of
+    # eqs. (6)-(7) and the unbounded case of Section 2.2 (scanned windows).
+    forms = {}
+    sc_f = torch.empty(1, dtype=torch.int32, device=dev)
+    xs_f = torch.empty(k + 1, dtype=torch.int32, device=dev)
+    for name, kw in [("shift_bound_8", dict(bend=B)), ("angle_10deg", dict(gamma=math.radians(10))),
+                     ("angle_30deg", dict(gamma=math.radians(30))),
+                     ("unbounded", dict(bend=2 * (h // k) - 2))]:
+        bb = fhtp.make_bend(kw.get("bend"), kw.get("gamma"))
+        wsf = torch.empty(fhtp.dp_workspace_bytes(h, w, k, bb), dtype=torch.uint8, device=dev)
+        forms[name] = round(time_events(
+            lambda: fhtp.polyline_dp(tables, h, w, k, ws=wsf, score=sc_f, xs=xs_f, stream=stream,
+                                     **kw), max(3, args.steps // 5), stream), 4)
+        del wsf
+    line["dp_ms_by_bend_form"] = forms
     if args.batch_images > 0:
         line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream)
     if args.serve_requests > 0:

@@ -108,6 +108,19 @@ def test_detect_angle_bound(dev, F, orc, gamma):
         assert host(xs).tolist() == want_x.tolist()
 
 
+@pytest.mark.parametrize("bend_kw", [dict(gamma=math.radians(10)), dict(gamma=math.radians(45)),
+                                     dict(bend=24), dict(bend=254)],
+                         ids=["angle10", "angle45", "bound24", "unbounded"])
+def test_full_size_generic_windows(dev, F, orc, bend_kw):
+    """The 4096x4096 k=32 image with the scanned windows: angle form, a large bound, none."""
+    s = synth.make_c3()
+    want_s, want_x = orc.detect_polyline(s.image, s.k, **bend_kw)
+    announce(f"detect C3 {bend_kw}")
+    sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, **bend_kw)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
 EDGE = [
     # (h, w, k, dtype, maxval, B)
     (8, 1, 8, np.uint8, 3, 0),        # n = 1, w = 1
