@@ -509,6 +509,46 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     }
     auto lo_of = [&](int j) { return __builtin_amdgcn_readlane(wlo, j); };
     auto hi_of = [&](int j) { return __builtin_amdgcn_readlane(whi, j); };
+    if (a.full) {
+        // Section 2.2: every window is the whole column, so the workgroup's
+        // waves split the column's rows, and the smallest row reaching the
+        // maximum wins across them (ties to the lower wave).
+        __shared__ int col_v[kWaves][64];
+        __shared__ int col_i[kWaves][64];
+        const int rows = (D + kWaves - 1) / kWaves;
+        const int r_lo = wave * rows, r_hi = min(D, r_lo + rows);
+        int cv = kEmpty, ci = 0;
+        for (int t0 = r_lo; t0 < r_hi; t0 += kScanTile) {
+            int v[kScanTile];
+#pragma unroll
+            for (int q = 0; q < kScanTile; ++q)
+                v[q] = load_v(a.vin, a.vin_pitch, xp, t0 + q - (n - 1), n, mk);
+#pragma unroll
+            for (int q = 0; q < kScanTile; ++q) {
+                const bool take = t0 + q < r_hi && v[q] > cv;
+                cv = take ? v[q] : cv;
+                ci = take ? t0 + q - (n - 1) : ci;
+            }
+        }
+        col_v[wave][lane] = cv;
+        col_i[wave][lane] = ci;
+        __syncthreads();
+        int m = col_v[0][lane], ia = col_i[0][lane];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) {
+            const bool take = col_v[q][lane] > m;
+            m = take ? col_v[q][lane] : m;
+            ia = take ? col_i[q][lane] : ia;
+        }
+        unsigned long long best = 0;
+#pragma unroll
+        for (int j = 0; j < kDCGeneric; ++j) {
+            if (j >= jn) break;
+            emit<AT>(a, m, ia + n - 1, hv[j], xp, d0 + j, best);
+        }
+        finish(a, best, local);
+        return;
+    }
     for (int ja = 0; ja < jn;) {
         const int c = hi_of(ja);
         int jb = ja;
