@@ -30,8 +30,8 @@ HBM_PEAK_GBPS = 8000.0
 # then WRITE_SIZE), each scaled by what the same counter reads for a copy of a
 # known size in the same run.  Valid only for the kernel source they were
 # taken on (sha256 of csrc/fhtp_fht.hip); otherwise the traffic is unknown.
-FHT_TRAFFIC = {"source_sha256": "58d93499356e2f49407fccf1cc43e95be8c9c7157d2b758f8b52e5f759d4729b",
-               "fetch_bytes": 36162244, "write_bytes": 140754944}
+FHT_TRAFFIC = {"source_sha256": "b58ad63c9c5f8b9312003c86060e83637f6b1908ce53c21aeb40e01c67fcc797",
+               "fetch_bytes": 36169317, "write_bytes": 140754944}
 
 
 def byte_model(h, w, k, bpp):
