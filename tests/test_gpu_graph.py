@@ -55,3 +55,56 @@ def test_graph_replays_match_eager(cfg):
         g_s, g_x = fhtp.detect_polyline(img2, s.k, bend=s.bend)
         torch.cuda.synchronize()
         assert np.array_equal(host(g_s), o_s) and np.array_equal(host(g_x), o_x)
+
+
+def test_graph_replays_batch_and_options():
+    """A batched call and a smoothed, pinned, horizontal call captured together."""
+    from paper_1912_01884_amd import fhtp
+    dev = require_gpu()
+    batch = synth.make_c4_batch(24)
+    imgs = [to_device(s.image, dev) for s in batch]
+    ks = [s.k for s in batch]
+    bends = [s.bend for s in batch]
+    ex_img = to_device(synth.make_config("C2").image, dev)
+    announce("graph eager batch + ex")
+    eager = [(host(a), host(b)) for a, b in fhtp.detect_batch(imgs, ks, bends=bends)]
+    e_s, e_x = [host(t) for t in fhtp.detect_polyline_ex(ex_img, 16, bend=4, smooth_radius=2,
+                                                          horizontal=True, pin=(8, 300))]
+    jobs, keep = fhtp.make_jobs(imgs, ks, bends=bends)
+    nb = fhtp.batch_workspace_bytes(jobs)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    b = fhtp.make_bend(4)
+    opt = fhtp.make_options(2, True, (8, 300))
+    ws2 = torch.empty(fhtp.detect_ex_workspace_bytes(fhtp.FHTP_U8, 1024, 1024, 16, b, opt),
+                      dtype=torch.uint8, device=dev)
+    sc2 = torch.empty(1, dtype=torch.int32, device=dev)
+    xs2 = torch.empty(17, dtype=torch.int32, device=dev)
+    import ctypes as C
+    arr = (fhtp.Job * len(jobs))(*jobs)
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream(dev)
+    cap.wait_stream(torch.cuda.current_stream(dev))
+    announce("graph capture batch + ex")
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            rc = fhtp.lib().fhtp_detect_batch(arr, len(jobs), C.c_void_p(ws.data_ptr()), nb,
+                                             C.c_void_p(cap.cuda_stream))
+            assert rc == 0
+            fhtp.detect_polyline_ex(ex_img, 16, bend=4, smooth_radius=2, horizontal=True,
+                                    pin=(8, 300), ws=ws2, score=sc2, xs=xs2, stream=cap)
+    torch.cuda.current_stream(dev).wait_stream(cap)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for sc, x in keep:
+            sc.fill_(-7)
+            x.fill_(-7)
+        sc2.fill_(-7)
+        announce(f"graph replay batch + ex #{rep}")
+        graph.replay()
+        torch.cuda.synchronize()
+        for (sc, x), (w_s, w_x) in zip(keep, eager):
+            assert np.array_equal(host(sc), w_s) and np.array_equal(host(x), w_x), rep
+        assert np.array_equal(host(sc2), e_s) and np.array_equal(host(xs2), e_x), rep
+        # eager work between replays
+        fhtp.detect_polyline(imgs[0], ks[0], bend=bends[0])
+        torch.cuda.synchronize()
