@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -413,6 +414,63 @@ int fhtp_batch_workspace_bytes(const fhtp_job* jobs, int count, size_t* bytes) {
     return FHTP_OK;
 }
 
+namespace {
+
+// A second stream per device for batches: the images whose tall bands take
+// the two-pass FHT and 16-bit back-pointers run their whole pipeline there,
+// the others on the caller's stream, so the two chains of dependent DP steps
+// (each bound by latency, not by the chip) overlap.  The caller's stream
+// forks to it with an event and joins back with another, so graph capture
+// sees a closed fork/join.  Created on first use outside graph capture (a call
+// under capture that finds it missing runs on one stream) and kept until the
+// process ends; streams keep the default priority.
+constexpr int kMaxDevices = 64;
+
+struct Aux {
+    std::mutex mu;
+    bool tried = false;
+    bool ok = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+Aux g_aux[kMaxDevices];
+
+Aux* aux_for_current_device(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    Aux& a = g_aux[dev];
+    std::lock_guard<std::mutex> lock(a.mu);
+    if (a.tried) return a.ok ? &a : nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    a.tried = true;
+    a.ok = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&a.join, hipEventDisableTiming) == hipSuccess;
+    (void)hipGetLastError();
+    return a.ok ? &a : nullptr;
+}
+
+// FHT then DP of a subset of a batch on one stream.
+int run_subset(const std::vector<fhtp::FhtJobSpec>& fj, const std::vector<fhtp::DpJobSpec>& dj,
+               const std::vector<int>& pick, hipStream_t s) {
+    std::vector<fhtp::FhtJobSpec> f;
+    std::vector<fhtp::DpJobSpec> d;
+    for (int q : pick) {
+        f.push_back(fj[q]);
+        d.push_back(dj[q]);
+    }
+    int rc = hip_status(fhtp::launch_fht_jobs(f.data(), (int)f.size(), s), "detect_batch/fht");
+    if (rc != FHTP_OK) return rc;
+    return hip_status(fhtp::launch_dp_jobs(d.data(), (int)d.size(), s), "detect_batch/dp");
+}
+
+}  // namespace
+
 int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, void* stream) {
     std::vector<BatchEntry> plan_v;
     size_t total = 0;
@@ -433,9 +491,25 @@ int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    rc = hip_status(fhtp::launch_fht_jobs(fj.data(), count, s), "detect_batch/fht");
+    std::vector<int> tall, rest;
+    for (int q = 0; q < count; ++q) (dj[q].plan.a16 ? tall : rest).push_back(q);
+    Aux* ax = (!tall.empty() && !rest.empty()) ? aux_for_current_device(s) : nullptr;
+    if (!ax) {
+        rc = hip_status(fhtp::launch_fht_jobs(fj.data(), count, s), "detect_batch/fht");
+        if (rc != FHTP_OK) return rc;
+        return hip_status(fhtp::launch_dp_jobs(dj.data(), count, s), "detect_batch/dp");
+    }
+    std::lock_guard<std::mutex> lock(ax->mu);
+    rc = hip_status(hipEventRecord(ax->fork, s), "detect_batch/fork");
+    if (rc == FHTP_OK) rc = hip_status(hipStreamWaitEvent(ax->stream, ax->fork, 0), "detect_batch/fork");
     if (rc != FHTP_OK) return rc;
-    return hip_status(fhtp::launch_dp_jobs(dj.data(), count, s), "detect_batch/dp");
+    const int rc_tall = run_subset(fj, dj, tall, ax->stream);
+    const int rc_rest = rc_tall == FHTP_OK ? run_subset(fj, dj, rest, s) : FHTP_OK;
+    // join even after an error, so that a capture is never left forked
+    int rc_join = hip_status(hipEventRecord(ax->join, ax->stream), "detect_batch/join");
+    if (rc_join == FHTP_OK)
+        rc_join = hip_status(hipStreamWaitEvent(s, ax->join, 0), "detect_batch/join");
+    return rc_tall != FHTP_OK ? rc_tall : rc_rest != FHTP_OK ? rc_rest : rc_join;
 }
 
 }  // extern "C"
