@@ -56,13 +56,9 @@ int pixels(fhtp_dtype dtype, int h) {
 }
 
 // Displacements per thread of the fixed-window DP step: 8 gives twice the
-// waves of 16 at the cost of more halo loads (from cache); FHTP_DP_DC overrides.
+// waves of 16 at the cost of more halo loads (from cache), which pays until
+// the grid fills the chip twice over.
 int dp_chunk(const fhtp::Geometry& g) {
-    const char* env = std::getenv("FHTP_DP_DC");
-    if (env) {
-        const int v = std::atoi(env);
-        if (v == 8 || v == 16) return v;
-    }
     const long long threads16 = (long long)g.w * ((g.D + 15) / 16);
     return threads16 < 256LL * 4 * 64 * 2 ? 8 : 16;
 }
