@@ -1,6 +1,6 @@
 """Throughput of the FHT + bend-limited DP polyline detector on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config C3]
+    python bench.py [--steps K] [--warmup W] [--config 4096x4096]
 
 One step is one whole detection (band FHT of all k bands, the DP over every
 band boundary, the argmax and the backtrace) of one seeded synthetic image
@@ -88,7 +88,7 @@ def mixed_batch(n_images, reps, dev, stream):
     import synth
     from paper_1912_01884_amd import fhtp
 
-    batch = synth.make_c4_batch(n_images)
+    batch = synth.make_mixed_batch(n_images)
     imgs = [torch.from_numpy(s.image).to(dev) for s in batch]
     jobs, keep = fhtp.make_jobs(imgs, [s.k for s in batch], bends=[s.bend for s in batch])
     L = fhtp.lib()
@@ -144,7 +144,7 @@ def serving(dev, rates, count, streams=4, max_batch=256):
     from paper_1912_01884_amd.serve import (FhtpBackend, PlainServer, Request, Server,
                                             poisson_arrivals, run_open_loop)
 
-    batch = synth.make_c4_batch(256)
+    batch = synth.make_mixed_batch(256)
     imgs = [torch.from_numpy(s.image).to(dev) for s in batch]
     pick = np.random.default_rng([191201884, 5, 998]).integers(0, len(batch), size=count)
     scores = torch.zeros((2, count), dtype=torch.int32, device=dev)
@@ -201,7 +201,7 @@ def probe(dev):
     import synth
     from paper_1912_01884_amd import fhtp
 
-    s = synth.make_c3()
+    s = synth.make_large()
     img = torch.from_numpy(s.image).to(dev)
     a = torch.empty(64 << 20, dtype=torch.int32, device=dev)
     b = torch.empty_like(a)
@@ -220,7 +220,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="C3", choices=["C1", "C2", "C3"])
+    ap.add_argument("--config", default="4096x4096", choices=["64x64", "1024x1024", "4096x4096"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-images", type=int, default=256,
@@ -325,7 +325,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {h}x{w} {s.image.dtype.name} image, k={k} "
+        "config": {"workload": f"{h}x{w} {s.image.dtype.name} image, k={k} "
                                f"bands of {h // k} rows, bend bound {B} shifts, one image per step",
                    "h": h, "w": w, "k": k, "bend": B, "pixel": s.image.dtype.name},
         "images_per_s": round(1e3 / ms_per_step, 2),

@@ -11,11 +11,11 @@ from .images import (  # noqa: F401
     SynthImage,
     draw_polyline,
     random_walk_shifts,
-    make_c1,
-    make_c2,
-    make_c3,
-    make_c4_image,
-    make_c4_batch,
+    make_small,
+    make_medium,
+    make_large,
+    make_mixed_image,
+    make_mixed_batch,
     make_config,
     CONFIGS,
 )

@@ -143,7 +143,7 @@ def _poly_record(x0, d, value, width) -> Polyline:
     return Polyline(x=x, d=d.astype(np.int64), value=int(value), width=int(width))
 
 
-def make_c1(image: int = 0) -> SynthImage:
+def make_small(image: int = 0) -> SynthImage:
     """64x64 uint8, k=4 (16-row bands): N(20,10) noise, one 1-px polyline of value 200, bend 1."""
     rng = rng_for(1, image)
     h = w = 64
@@ -152,10 +152,10 @@ def make_c1(image: int = 0) -> SynthImage:
     img = _gauss_bg(rng, (h, w), 20.0, 10.0)
     x0, d = draw_shifts_and_start(rng, k, R, B, w, uniform=True)
     draw_polyline(img, x0, d, n, 1, 200)
-    return SynthImage(img, h, w, k, B, [_poly_record(x0, d, 200, 1)], "C1")
+    return SynthImage(img, h, w, k, B, [_poly_record(x0, d, 200, 1)], "64x64")
 
 
-def _c2_like(rng, h, w, k, B, n_curves=3) -> Tuple[np.ndarray, List[Polyline]]:
+def _noisy_curves(rng, h, w, k, B, n_curves=3) -> Tuple[np.ndarray, List[Polyline]]:
     n = h // k
     R = max(1, n // 4)
     img = _gauss_bg(rng, (h, w), 30.0, 15.0)
@@ -175,16 +175,16 @@ def _c2_like(rng, h, w, k, B, n_curves=3) -> Tuple[np.ndarray, List[Polyline]]:
     return img, polys
 
 
-def make_c2(image: int = 0) -> SynthImage:
+def make_medium(image: int = 0) -> SynthImage:
     """1024x1024 uint8, k=16 (64-row bands): N(30,15) noise, 3 polylines, 10% occluded, bend 4."""
     rng = rng_for(2, image)
     h = w = 1024
     k, B = 16, 4
-    img, polys = _c2_like(rng, h, w, k, B)
-    return SynthImage(img, h, w, k, B, polys, "C2")
+    img, polys = _noisy_curves(rng, h, w, k, B)
+    return SynthImage(img, h, w, k, B, polys, "1024x1024")
 
 
-def make_c3(image: int = 0, h: int = 4096, w: int = 4096, k: int = 32) -> SynthImage:
+def make_large(image: int = 0, h: int = 4096, w: int = 4096, k: int = 32) -> SynthImage:
     """4096x4096 uint16, k=32 (128-row bands): Exp(500) noise plus 8 additive polylines, bend 8."""
     rng = rng_for(3, image)
     B = 8
@@ -198,44 +198,44 @@ def make_c3(image: int = 0, h: int = 4096, w: int = 4096, k: int = 32) -> SynthI
         x0, d = draw_shifts_and_start(rng, k, R, B, w)
         draw_polyline(img, x0, d, n, 1, amp, additive=True)
         polys.append(_poly_record(x0, d, amp, 1))
-    return SynthImage(img, h, w, k, B, polys, "C3")
+    return SynthImage(img, h, w, k, B, polys, "4096x4096")
 
 
-C4_HEIGHTS = (128, 256, 512, 1024, 2048)
-C4_KS = (4, 8, 16)
+MIXED_HEIGHTS = (128, 256, 512, 1024, 2048)
+MIXED_KS = (4, 8, 16)
 
 
-def make_c4_image(image: int) -> SynthImage:
+def make_mixed_image(image: int) -> SynthImage:
     """One image of the mixed-size batch: h in {128..2048}, w ~ U{256..2048}, k in {4,8,16}."""
     rng = rng_for(4, image)
-    h = int(rng.choice(C4_HEIGHTS))
+    h = int(rng.choice(MIXED_HEIGHTS))
     w = int(rng.integers(256, 2049))
-    k = int(rng.choice(C4_KS))
+    k = int(rng.choice(MIXED_KS))
     B = 4
-    img, polys = _c2_like(rng, h, w, k, B)
-    return SynthImage(img, h, w, k, B, polys, "C4")
+    img, polys = _noisy_curves(rng, h, w, k, B)
+    return SynthImage(img, h, w, k, B, polys, "mixed")
 
 
-def make_c4_batch(count: int = 256) -> List[SynthImage]:
-    return [make_c4_image(j) for j in range(count)]
+def make_mixed_batch(count: int = 256) -> List[SynthImage]:
+    return [make_mixed_image(j) for j in range(count)]
 
 
 CONFIGS = {
-    "C1": dict(h=64, w=64, k=4, bend=1, dtype="u8"),
-    "C2": dict(h=1024, w=1024, k=16, bend=4, dtype="u8"),
-    "C3": dict(h=4096, w=4096, k=32, bend=8, dtype="u16"),
+    "64x64": dict(h=64, w=64, k=4, bend=1, dtype="u8"),
+    "1024x1024": dict(h=1024, w=1024, k=16, bend=4, dtype="u8"),
+    "4096x4096": dict(h=4096, w=4096, k=32, bend=8, dtype="u16"),
 }
 
 
 def make_config(name: str, image: int = 0) -> SynthImage:
-    if name == "C1":
-        return make_c1(image)
-    if name == "C2":
-        return make_c2(image)
-    if name == "C3":
-        return make_c3(image)
-    if name == "C4":
-        return make_c4_image(image)
+    if name == "64x64":
+        return make_small(image)
+    if name == "1024x1024":
+        return make_medium(image)
+    if name == "4096x4096":
+        return make_large(image)
+    if name == "mixed":
+        return make_mixed_image(image)
     raise ValueError(f"unknown config {name!r}")
 
 

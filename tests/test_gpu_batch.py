@@ -62,7 +62,7 @@ def test_mixed_size_workload_batch_matches_single():
     """All 256 images of the mixed-size workload, batched vs one at a time."""
     from paper_1912_01884_amd import fhtp
     dev = require_gpu()
-    batch = synth.make_c4_batch(256)
+    batch = synth.make_mixed_batch(256)
     imgs = [to_device(s.image, dev) for s in batch]
     ks = [s.k for s in batch]
     bends = [s.bend for s in batch]
@@ -78,7 +78,7 @@ def test_mixed_size_workload_batch_matches_single():
 def test_batch_repeat_identical():
     from paper_1912_01884_amd import fhtp
     dev = require_gpu()
-    batch = synth.make_c4_batch(40)
+    batch = synth.make_mixed_batch(40)
     imgs = [to_device(s.image, dev) for s in batch]
     announce("batch repeat 40")
     a = fhtp.detect_batch(imgs, [s.k for s in batch], bends=[s.bend for s in batch])

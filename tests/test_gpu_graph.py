@@ -15,7 +15,7 @@ from tests.gpu_util import announce, host, require_gpu, to_device
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg", ["C1", "C2", "C3"])
+@pytest.mark.parametrize("cfg", ["64x64", "1024x1024", "4096x4096"])
 def test_graph_replays_match_eager(cfg):
     from paper_1912_01884_amd import fhtp
     dev = require_gpu()
@@ -61,11 +61,11 @@ def test_graph_replays_batch_and_options():
     """A batched call and a smoothed, pinned, horizontal call captured together."""
     from paper_1912_01884_amd import fhtp
     dev = require_gpu()
-    batch = synth.make_c4_batch(24)
+    batch = synth.make_mixed_batch(24)
     imgs = [to_device(s.image, dev) for s in batch]
     ks = [s.k for s in batch]
     bends = [s.bend for s in batch]
-    ex_img = to_device(synth.make_config("C2").image, dev)
+    ex_img = to_device(synth.make_config("1024x1024").image, dev)
     announce("graph eager batch + ex")
     eager = [(host(a), host(b)) for a, b in fhtp.detect_batch(imgs, ks, bends=bends)]
     e_s, e_x = [host(t) for t in fhtp.detect_polyline_ex(ex_img, 16, bend=4, smooth_radius=2,

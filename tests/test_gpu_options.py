@@ -83,14 +83,14 @@ def test_through_point_matches_oracle(F, orc, dev, h, w, k, dtype, bk):
 
 
 def test_through_point_on_the_best_polyline_is_the_free_result(F, orc, dev):
-    si = synth.make_c2()
+    si = synth.make_medium()
     img = si.image
     d = to_device(img, dev)
     s, xs = F.detect_polyline(d, si.k, bend=si.bend)
     torch.cuda.synchronize()
     s, xs = int(host(s)[0]), host(xs)
     for j in (0, 5, si.k):
-        announce(f"through_point c2 on the free optimum j={j}")
+        announce(f"through_point 1024x1024 on the free optimum j={j}")
         s2, xs2 = F.detect_polyline_ex(d, si.k, bend=si.bend, pin=(j, int(xs[j])))
         torch.cuda.synchronize()
         assert int(host(s2)[0]) == s and host(xs2).tolist() == xs.tolist()
@@ -127,7 +127,7 @@ def test_prepared_image_edge_shapes(F, orc, dev, shape):
             assert np.array_equal(host(out), orc.smooth_rows(src, r))
 
 
-@pytest.mark.parametrize("cfg,r", [("C1", 1), ("C2", 2), ("C2", 7)])
+@pytest.mark.parametrize("cfg,r", [("64x64", 1), ("1024x1024", 2), ("1024x1024", 7)])
 def test_smoothed_detection_matches_oracle(F, orc, dev, cfg, r):
     si = synth.make_config(cfg)
     announce(f"smoothed detect {cfg} r={r}")
@@ -154,11 +154,11 @@ def test_horizontal_matches_oracle(F, orc, dev, h, w, k, dtype, bk, r):
         _run(F, orc, dev, img, k, smooth_radius=r, horizontal=True, pin=(j, y), **bk)
 
 
-def test_horizontal_recovers_a_transposed_c2_curve(F, orc, dev):
+def test_horizontal_recovers_a_transposed_1024_curve(F, orc, dev):
     """The 1024^2 k=16 image turned on its side: the curve found is the same one."""
-    si = synth.make_c2()
+    si = synth.make_medium()
     img_t = np.ascontiguousarray(si.image.T)
-    announce("horizontal c2 transposed")
+    announce("horizontal 1024x1024 transposed")
     s, ys = _run(F, orc, dev, img_t, si.k, bend=si.bend, horizontal=True)
     s0, xs0 = orc.detect_polyline(si.image, si.k, bend=si.bend)
     assert s == s0 and ys.tolist() == xs0.tolist()
@@ -166,11 +166,11 @@ def test_horizontal_recovers_a_transposed_c2_curve(F, orc, dev):
 
 def test_full_size_options(F, orc, dev):
     """4096^2 uint16, k = 32, B = 8 with smoothing and a pin in the middle boundary."""
-    si = synth.make_c3()
+    si = synth.make_large()
     s0, xs0 = orc.detect_polyline(si.image, si.k, bend=si.bend)
-    announce("c3 pinned through the free optimum, r=0")
+    announce("4096x4096 pinned through the free optimum, r=0")
     _run(F, orc, dev, si.image, si.k, bend=si.bend, pin=(16, int(xs0[16])))
-    announce("c3 smoothed r=2, pinned at column 1000 of boundary 16")
+    announce("4096x4096 smoothed r=2, pinned at column 1000 of boundary 16")
     _run(F, orc, dev, si.image, si.k, bend=si.bend, smooth_radius=2, pin=(16, 1000))
 
 

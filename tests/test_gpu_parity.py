@@ -68,7 +68,7 @@ def test_tables_small(dev, F, orc, h, w, k, dtype, vals):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("cfg", ["C1", "C2", "C3"])
+@pytest.mark.parametrize("cfg", ["64x64", "1024x1024", "4096x4096"])
 def test_tables_configs(dev, F, orc, cfg):
     s = synth.make_config(cfg)
     want = orc.fht_bands(s.image, s.k)
@@ -77,7 +77,7 @@ def test_tables_configs(dev, F, orc, cfg):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("cfg", ["C1", "C2", "C3"])
+@pytest.mark.parametrize("cfg", ["64x64", "1024x1024", "4096x4096"])
 def test_detect_configs(dev, F, orc, cfg):
     s = synth.make_config(cfg)
     want_s, want_x = orc.detect_polyline(s.image, s.k, bend=s.bend)
@@ -89,9 +89,9 @@ def test_detect_configs(dev, F, orc, cfg):
 
 @pytest.mark.parametrize("B", [0, 1, 2, 5, 8, 16, 17, 29, 30, 100])
 def test_detect_c1_every_window_kind(dev, F, orc, B):
-    s = synth.make_c1()
+    s = synth.make_small()
     want_s, want_x = orc.detect_polyline(s.image, s.k, bend=B)
-    announce(f"detect C1 B={B}")
+    announce(f"detect 64x64 B={B}")
     sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, bend=B)
     assert int(host(sc)[0]) == want_s
     assert host(xs).tolist() == want_x.tolist()
@@ -99,7 +99,7 @@ def test_detect_c1_every_window_kind(dev, F, orc, B):
 
 @pytest.mark.parametrize("gamma", [0.0, 0.05, 0.2, math.radians(10), 1.0, math.pi / 2, 2.0])
 def test_detect_angle_bound(dev, F, orc, gamma):
-    for cfg in ("C1", "C2"):
+    for cfg in ("64x64", "1024x1024"):
         s = synth.make_config(cfg)
         want_s, want_x = orc.detect_polyline(s.image, s.k, gamma=gamma)
         announce(f"detect {cfg} gamma={gamma}")
@@ -113,9 +113,9 @@ def test_detect_angle_bound(dev, F, orc, gamma):
                          ids=["angle10", "angle45", "bound24", "unbounded"])
 def test_full_size_generic_windows(dev, F, orc, bend_kw):
     """The 4096x4096 k=32 image with the scanned windows: angle form, a large bound, none."""
-    s = synth.make_c3()
+    s = synth.make_large()
     want_s, want_x = orc.detect_polyline(s.image, s.k, **bend_kw)
-    announce(f"detect C3 {bend_kw}")
+    announce(f"detect 4096x4096 {bend_kw}")
     sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, **bend_kw)
     assert int(host(sc)[0]) == want_s
     assert host(xs).tolist() == want_x.tolist()
@@ -179,19 +179,19 @@ def test_detect_random_tiny(dev, F, orc, seed):
 
 
 def test_polyline_dp_on_oracle_tables(dev, F, orc):
-    s = synth.make_c2()
+    s = synth.make_medium()
     tables = orc.fht_bands(s.image, s.k)
     want_s, want_x = orc.polyline_dp(tables, s.h, s.w, s.k, bend=s.bend)
-    announce("polyline_dp C2 on oracle tables")
+    announce("polyline_dp 1024x1024 on oracle tables")
     sc, xs = F.polyline_dp(to_device(tables, dev), s.h, s.w, s.k, bend=s.bend)
     assert int(host(sc)[0]) == want_s
     assert host(xs).tolist() == want_x.tolist()
 
 
 def test_repeat_runs_identical(dev, F):
-    s = synth.make_c2()
+    s = synth.make_medium()
     img = to_device(s.image, dev)
-    announce("determinism C2")
+    announce("determinism 1024x1024")
     t1 = host(F.fht_bands(img, s.k))
     t2 = host(F.fht_bands(img, s.k))
     assert np.array_equal(t1, t2)
@@ -203,7 +203,7 @@ def test_repeat_runs_identical(dev, F):
 @pytest.mark.parametrize("j", range(0, 256, 16))
 def test_detect_mixed_batch_images(dev, F, orc, j):
     """Images of the mixed-size batch workload (h 128..2048, w 256..2048, k 4..16)."""
-    s = synth.make_c4_image(j)
+    s = synth.make_mixed_image(j)
     want_s, want_x = orc.detect_polyline(s.image, s.k, bend=s.bend)
     announce(f"detect mixed image {j}: {s.h}x{s.w} k={s.k}")
     sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, bend=s.bend)

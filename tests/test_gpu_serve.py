@@ -23,7 +23,7 @@ def dev():
 
 @pytest.fixture(scope="module")
 def mix(dev):
-    batch = synth.make_c4_batch(48)
+    batch = synth.make_mixed_batch(48)
     return batch, [to_device(s.image, dev) for s in batch]
 
 

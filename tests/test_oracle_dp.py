@@ -66,9 +66,9 @@ def test_brute_force_tiny_mode1(orc, n, k, w):
             assert got_x.tolist() == want_x, (trial, g)
 
 
-def test_brute_force_whole_c1(orc):
+def test_brute_force_whole_64x64(orc):
     """Every admissible polyline of the 64x64 k=4 configuration, scores walked pixel by pixel."""
-    s = synth.make_c1()
+    s = synth.make_small()
     img = s.image.astype(np.int64)
     h, w, k, B = s.h, s.w, s.k, s.bend
     n = h // k
@@ -286,7 +286,7 @@ def _check_invariants(img, k, B, score, xs):
 
 
 def test_c2_invariants_and_local_optimality(orc):
-    s = synth.make_c2()
+    s = synth.make_medium()
     score, xs = orc.detect_polyline(s.image, s.k, bend=s.bend)
     ds = _check_invariants(s.image, s.k, s.bend, score, xs)
     # No single-vertex move (keeping everything else) finds a better admissible polyline.

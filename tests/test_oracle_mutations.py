@@ -63,7 +63,7 @@ def _pins():
                                         for a in [(2, 2, 5), (4, 2, 5), (4, 3, 3), (2, 3, 8)]]),
         ("brute_tiny_mode1", lambda o: [tdp.test_brute_force_tiny_mode1(o, *a)
                                         for a in [(4, 2, 6), (8, 2, 9)]]),
-        ("brute_c1", tdp.test_brute_force_whole_c1),
+        ("brute_64x64", tdp.test_brute_force_whole_64x64),
         ("zero_constant", lambda o: tdp.test_zero_and_constant(o, 64, 50, 4, 1)),
         ("planted", lambda o: [tdp.test_planted_model_polyline(o, s) for s in range(3)]),
         ("unconstrained", lambda o: tdp.test_unconstrained_equals_column_max_dp(o, 64, 64, 4)),
