@@ -236,7 +236,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
-              "(the detector runs one image per GPU; see DESIGN.md for how it would shard)",
+              "(independent images and requests would shard one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -92,7 +92,7 @@ def lib() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
-                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+                           "`python -m paper_1912_01884_amd.build`")
     L = C.CDLL(LIB_PATH)
     vp, sz, i32, i64p = C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_int64)
     szp = C.POINTER(C.c_size_t)
