@@ -467,6 +467,171 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
     finish(a, best, local);
 }
 
+// ---- two steps per launch (fixed mode-0 window) -------------------------------
+//
+// A step reads V_{i+1} only in the successor columns it owns and in the rows
+// of its displacements widened by B on either side, so a workgroup can make
+// those cells of V_{i+1} itself from V_{i+2} and go straight on to step i:
+//
+//   phase 1: V_{i+1}(x', d') for x' in its 64 columns and d' in its rows
+//            widened by B, into LDS, as the step for band i+1 computes them
+//            (successor column x'' = x' + d', window of V_{i+2} in that
+//            column); the back-pointers A_{i+2} of the cells in its own rows
+//            go to memory;
+//   phase 2: step i from LDS, writing V_i and A_{i+1}.
+//
+// V_{i+1} then never goes through memory and the chain of dependent launches
+// is half as long.  The cells of the widened rows are recomputed by the
+// neighbouring workgroups (2B rows on top of 32).  Phase 1 runs in strips of
+// kStrip rows: a strip's cells lie in 64 + kStrip - 1 successor columns, one
+// thread each.
+constexpr int kPairWaves = 4;                    // waves per workgroup
+constexpr int kPairDC = 8;                       // phase 2: displacements per thread
+constexpr int kPairRows = kPairWaves * kPairDC;  // displacements of step i per workgroup
+constexpr int kStrip = 16;                       // phase 1: displacements per thread
+
+struct DpPairJob {
+    const int32_t* vin;  // V_{i+2} (or the table H_{k-1}), rows d''+n-1
+    const int32_t* h1;   // H_{i+1}
+    const int32_t* h0;   // H_i
+    int32_t* vout;       // V_i
+    void* a1;            // A_{i+2} plane
+    void* a0;            // A_{i+1} plane
+    int vin_pitch, h_pitch, v_pitch, a_pitch;
+    int n, w, items_x;
+};
+
+template <int B, typename AT>
+__global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
+    constexpr int RM = kPairRows + 2 * B;  // rows of V_{i+1} the workgroup needs
+    constexpr int NS = (RM + kStrip - 1) / kStrip;
+    constexpr int SC = 64 + kStrip - 1;    // successor columns of one strip
+    constexpr int NV1 = kStrip + 2 * B;
+    constexpr int NV2 = kPairDC + 2 * B;
+    constexpr int esz = (int)sizeof(AT);
+    __shared__ int mid[RM][64];  // V_{i+1}(X0 + lane, row m0 + q)
+
+    const int n = a.n, w = a.w;
+    const int D = 2 * n - 1;
+    const int bx = blockIdx.x % a.items_x, by = blockIdx.x / a.items_x;
+    const int X0 = bx * 64;
+    const int r0 = by * kPairRows;  // table row of the first displacement of step i
+    const int m0 = r0 - B;          // table row of mid[0]
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    // Phase 2's H_i(x' - d, d), issued first so that the loads overlap phase 1.
+    const int xp = X0 + lane;
+    const bool col_ok = xp < w;
+    const int r2 = r0 + wave * kPairDC;
+    const int d2 = r2 - (n - 1);
+    const RowView h0v = row_view(a.h0, a.h_pitch, 4, r2, kPairDC, D);
+    int hv0[kPairDC];
+#pragma unroll
+    for (int j = 0; j < kPairDC; ++j) {
+        const int x = xp - d2 - j;
+        const bool ok = col_ok && r2 + j < D && (unsigned)x < (unsigned)w;
+        const int t = __builtin_amdgcn_raw_buffer_load_b32(
+            h0v.rs, (int)(ok ? (unsigned int)x * 4u : kOut),
+            (int)row_off(h0v, r2 + j, a.h_pitch, 4), 0);
+        hv0[j] = ok ? t : 0;
+    }
+
+    // Phase 1.  Views: V_{i+2} rows [m0 - B, m0 + NS*kStrip + B), H_{i+1} rows
+    // [m0, m0 + RM), A_{i+2} rows [r0, r0 + kPairRows), each clipped to [0, D);
+    // every access below checks its row against [0, D) and the view's range.
+    const RowView vv = row_view(a.vin, a.vin_pitch, 4, m0 - B, NS * kStrip + 2 * B, D);
+    const RowView h1v = row_view(a.h1, a.h_pitch, 4, m0, RM, D);
+    const RowView a1v = row_view(a.a1, a.a_pitch, esz, r0, kPairRows, D);
+    const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
+    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
+    const unsigned int ap = (unsigned int)a.a_pitch * (unsigned int)esz;
+    for (int t = threadIdx.x; t < NS * SC; t += 64 * kPairWaves) {
+        const int s = t / SC, c = t - s * SC;
+        const int q0 = s * kStrip;       // mid row of the strip's first displacement
+        const int rs = m0 + q0;          // its table row
+        const int xs = X0 + rs - (n - 1) + c;  // successor column x''
+        const bool xs_ok = (unsigned)xs < (unsigned)w;
+        int v[NV1];
+#pragma unroll
+        for (int q = 0; q < NV1; ++q) {
+            const int row = rs - B + q;
+            const bool ok = xs_ok && row >= 0 && row < D &&
+                            (unsigned)(xs + row - (n - 1)) < (unsigned)w;
+            const int tv = __builtin_amdgcn_raw_buffer_load_b32(
+                vv.rs, (int)(ok ? (unsigned int)(row - vv.base) * vp + (unsigned int)xs * 4u : kOut),
+                0, 0);
+            v[q] = ok ? tv : -1;
+        }
+        // H_{i+1}(x', d') of the strip's cells in the tile: x' = X0 + c - j
+        int hv[kStrip];
+#pragma unroll
+        for (int j = 0; j < kStrip; ++j) {
+            const int row = rs + j;
+            const int x1 = X0 + c - j;
+            const bool ok = (unsigned)(c - j) < 64u && q0 + j < RM && row >= 0 && row < D &&
+                            x1 < w;
+            const int tv = __builtin_amdgcn_raw_buffer_load_b32(
+                h1v.rs, (int)(ok ? (unsigned int)(row - h1v.base) * hp + (unsigned int)x1 * 4u : kOut),
+                0, 0);
+            hv[j] = ok ? tv : 0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        int m[kStrip], ia[kStrip];
+        window_max<B, kStrip>(v, m, ia);
+#pragma unroll
+        for (int j = 0; j < kStrip; ++j) {
+            const int row = rs + j;
+            const int x1 = X0 + c - j;
+            const bool in = (unsigned)(c - j) < 64u && q0 + j < RM;
+            const bool live = in && xs_ok && row >= 0 && row < D && x1 < w;
+            const int val = live && m[j] >= 0 ? hv[j] + m[j] : -1;
+            if (in) mid[q0 + j][c - j] = val;
+            const bool own = live && row >= r0 && row < r0 + kPairRows;
+            const int ra = rs - B + ia[j];  // row of the maximum's d''
+            const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
+            const unsigned int off =
+                own ? (unsigned int)(row - a1v.base) * ap + (unsigned int)xs * (unsigned int)esz : kOut;
+            if constexpr (sizeof(AT) == 1)
+                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, a1v.rs, (int)off, 0, 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, a1v.rs, (int)off, 0, 0);
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: step i on the LDS copy of V_{i+1}; rows outside [0, D) and
+    // cells without a successor column hold -1.
+    int v2[NV2];
+#pragma unroll
+    for (int q = 0; q < NV2; ++q) v2[q] = mid[wave * kPairDC + q][lane];
+    int m2[kPairDC], ia2[kPairDC];
+    window_max<B, kPairDC>(v2, m2, ia2);
+    const RowView aview = row_view(a.a0, a.a_pitch, esz, r2, kPairDC, D);
+    const RowView oview = row_view(a.vout, a.v_pitch, 4, r2, kPairDC, D);
+#pragma unroll
+    for (int j = 0; j < kPairDC; ++j) {
+        const int r = r2 + j;
+        const int x = xp - d2 - j;
+        const bool cell = col_ok && r < D;
+        const bool live = cell && (unsigned)x < (unsigned)w;
+        const int val = m2[j] >= 0 ? hv0[j] + m2[j] : -1;
+        const unsigned int arow = row_off(aview, r, a.a_pitch, esz);
+        const unsigned int vrow = row_off(oview, r, a.v_pitch, 4);
+        const int ra = r2 - B + ia2[j];
+        const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
+        if constexpr (sizeof(AT) == 1)
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs,
+                                                 (int)(cell ? (unsigned int)xp : kOut), (int)arow, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs,
+                                                  (int)(cell ? (unsigned int)xp * 2u : kOut),
+                                                  (int)arow, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs,
+                                              (int)(live ? (unsigned int)x * 4u : kOut), (int)vrow, 0);
+    }
+}
+
 // Step with per-displacement windows [lo(d), hi(d)] (large mode-0 bounds, the
 // angle form, no bound at all).  Both window ends are non-decreasing in d, so
 // the windows of a wave's kDCGeneric displacements fall into groups that
@@ -902,6 +1067,104 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
     return hipSuccess;
 }
 
+template <typename AT>
+hipError_t launch_pair(int bound, hipStream_t s, int grid, const DpPairJob& a) {
+#define FHTP_B(BB)                                                                              \
+    case BB:                                                                                    \
+        hipLaunchKernelGGL((dp_pair_fixed<BB, AT>), dim3(grid), dim3(64 * kPairWaves), 0, s, a); \
+        return hipSuccess;
+    switch (bound) {
+        FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
+        FHTP_B(9) FHTP_B(10) FHTP_B(11) FHTP_B(12) FHTP_B(13) FHTP_B(14) FHTP_B(15) FHTP_B(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef FHTP_B
+}
+
+// Two steps per launch suit a single image whose step grid leaves the chip
+// latency-bound (the 8-displacement chunk), with the fixed window, no pin and
+// at least one pair of steps before the last; the byte offsets inside a
+// workgroup's rows must fit 32 bits.
+bool pairs_apply(const DpJobSpec& J) {
+    const Geometry& g = J.g;
+    const long long rows = kPairRows + 4LL * kMaxFixedB + kStrip;  // the widest view
+    const long long pitch = std::max(g.W, g.pitch);
+    return J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC && J.pin.j < 0 && g.k >= 4 &&
+           rows * pitch * 4 < 0x7fffffffLL;
+}
+
+// Steps of one image with bands k-2 .. 1 taken two per launch (one single
+// step first when their count is odd), then the last step.  The launches
+// that make V alternate between the two value planes so that V_1 lands in
+// plane 1, where the last step and the walk read it; a launch never writes
+// the plane it reads.
+template <typename AT>
+hipError_t run_steps_paired(const DpClass& c, const DpJobSpec& J, hipStream_t s) {
+    const Geometry& g = J.g;
+    const size_t band = (size_t)g.D * g.W;
+    const size_t plane = (size_t)g.D * g.pitch;
+    const int P = g.k - 2;                   // bands k-2 .. 1 before the last step
+    const int launches = (P & 1) + P / 2;   // launches that make V
+    const int items_x = (g.w + 63) / 64;
+    const int items_y = (g.D + kPairRows - 1) / kPairRows;
+    const int32_t* vin = J.tables + (size_t)(g.k - 1) * band;
+    int vin_pitch = g.W;
+    int i = g.k - 2;  // next band to make
+    for (int L = 0; L < launches; ++L) {
+        int32_t* vout = J.buf.vplanes + (size_t)(((launches - 1 - L) & 1) ? 0 : 1) * plane;
+        AT* A = static_cast<AT*>(J.buf.a);
+        if (L == 0 && (P & 1)) {
+            DpPack<1> pk{};
+            DpJob a = base_job(J);
+            a.vin = vin;
+            a.vin_pitch = vin_pitch;
+            a.htab = J.tables + (size_t)i * band;
+            a.vout = vout;
+            a.aout = A + (size_t)(i - 1) * plane;
+            a.item0 = 0;
+            pk.job[0] = a;
+            pk.count = 1;
+            pk.total = items_x * items_y_of(g, c.dc);
+            hipError_t e = launch_step<AT, 1>(c, s, pk);
+            if (e != hipSuccess) return e;
+            i -= 1;
+        } else {
+            // bands i (phase 1) and i-1 (phase 2)
+            DpPairJob a{};
+            a.vin = vin;
+            a.vin_pitch = vin_pitch;
+            a.h1 = J.tables + (size_t)i * band;
+            a.h0 = J.tables + (size_t)(i - 1) * band;
+            a.vout = vout;
+            a.a1 = A + (size_t)(i - 1) * plane;  // A_{i+1}
+            a.a0 = A + (size_t)(i - 2) * plane;  // A_i
+            a.h_pitch = g.W;
+            a.v_pitch = g.pitch;
+            a.a_pitch = g.pitch;
+            a.n = g.n;
+            a.w = g.w;
+            a.items_x = items_x;
+            hipError_t e = launch_pair<AT>(J.plan.bound, s, items_x * items_y, a);
+            if (e != hipSuccess) return e;
+            i -= 2;
+        }
+        vin = vout;
+        vin_pitch = g.pitch;
+    }
+    // last step: V_1 (plane 1) to the keys
+    DpPack<1> pk{};
+    DpJob a = base_job(J);
+    a.vin = J.buf.vplanes + plane;
+    a.vin_pitch = g.pitch;
+    a.htab = J.tables;
+    a.key = J.buf.key;
+    a.item0 = 0;
+    pk.job[0] = a;
+    pk.count = 1;
+    pk.total = items_x * items_y_of(g, c.dc);
+    return launch_step<AT, 1>(c, s, pk);
+}
+
 template <typename AT, int CAP>
 hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
     for (size_t q0 = 0; q0 < jobs.size(); q0 += CAP) {
@@ -982,7 +1245,8 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
         for (size_t q0 = 0; q0 < group.size(); q0 += CAP) {
             std::vector<const DpJobSpec*> pack(group.begin() + q0,
                                                group.begin() + std::min(group.size(), q0 + CAP));
-            hipError_t e = run_steps<AT, CAP>(c, pack, s);
+            hipError_t e = CAP == 1 && pairs_apply(*pack[0]) ? run_steps_paired<AT>(c, *pack[0], s)
+                                                             : run_steps<AT, CAP>(c, pack, s);
             if (e != hipSuccess) return e;
         }
     }

@@ -150,6 +150,28 @@ def test_detect_edges(dev, F, orc, h, w, k, dtype, maxval, B):
     assert host(xs).tolist() == want_x.tolist()
 
 
+PAIRED = [
+    # (h, w, k): a single image with the fixed window takes its steps two per
+    # launch; odd and even step counts, ragged widths, several row groups
+    (32 * 5, 333, 5),    # n = 32: one single step, then one pair
+    (64 * 8, 200, 8),    # n = 64: three pairs
+    (128 * 4, 130, 4),   # n = 128: one pair, 255 displacements
+    (16 * 9, 70, 9),     # n = 16: odd count
+    (8 * 12, 65, 12),    # n = 8: windows wider than the displacement range
+]
+
+
+@pytest.mark.parametrize("B", [0, 1, 3, 7, 8, 9, 12, 16])
+@pytest.mark.parametrize("h,w,k", PAIRED, ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in PAIRED])
+def test_detect_paired_steps(dev, F, orc, h, w, k, B):
+    img = _img(h, w, np.uint8, 31 * h + w + B, 3 if B % 2 == 0 else None)
+    want_s, want_x = orc.detect_polyline(img, k, bend=B)
+    announce(f"detect paired {h}x{w} k={k} B={B}")
+    sc, xs = F.detect_polyline(to_device(img, dev), k, bend=B)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
 def test_saturated_image(dev, F, orc):
     img = np.full((256, 301), 255, np.uint8)
     announce("detect saturated 256x301")
