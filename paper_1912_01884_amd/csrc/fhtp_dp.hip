@@ -50,6 +50,13 @@ constexpr int kMaxFixedB = 16; // largest bend bound with a register-window kern
 constexpr int kDCGeneric = 16; // displacements per thread in the scanning kernels
 constexpr int kPack = 256;     // images per launch (kernel arguments of up to 32 KB)
 
+// Cache policy of the value and back-pointer plane stores: device scope
+// (SC1), written through the XCD's L2.  The next launch reads the planes from
+// every XCD; written through, they reach memory while the kernel runs instead
+// of in the L2 write-back at its end, which sits on the critical path of the
+// chain of step launches (about 1.2 us per launch at 4096 x 255 cells).
+constexpr int kStoreScope = 16;
+
 // One image in one step launch.
 struct DpJob {
     const int32_t* vin;       // V_{i+1} (or the table H_{k-1}), rows d'+n-1
@@ -189,29 +196,6 @@ __device__ __forceinline__ int load_h(const DpJob& a, int xp, int d) {
     return ok ? v : 0;
 }
 
-// One output cell (x' = xp, displacement d) with range maximum m reached at row ra.
-template <typename AT>
-__device__ __forceinline__ void emit(const DpJob& a, int m, int ra, int hval, int xp, int d,
-                                     unsigned long long& best) {
-    const int n = a.n, w = a.w;
-    const int D = 2 * n - 1;
-    const int r = d + n - 1;
-    if (xp >= w || r >= D) return;
-    const bool last = a.key != nullptr;
-    if (!last)
-        static_cast<AT*>(a.aout)[(unsigned int)r * (unsigned int)a.a_pitch + (unsigned int)xp] =
-            (AT)(ra < 0 ? 0 : ra);
-    const int x = xp - d;
-    if (x < 0 || x >= w) return;
-    const int val = (m >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hval + m : -1;
-    if (last) {
-        const unsigned long long kk = pack_key(val, x, r, D);
-        best = kk > best ? kk : best;
-    } else {
-        a.vout[(unsigned int)r * (unsigned int)a.v_pitch + (unsigned int)x] = val;
-    }
-}
-
 // Common end of a step workgroup: on the image's last step its best key goes
 // to slot `slot` (its workgroup index within the image).
 __device__ __forceinline__ void finish(const DpJob& a, unsigned long long best, int slot) {
@@ -259,6 +243,39 @@ __device__ __forceinline__ unsigned int row_off(const RowView& v, int row, int p
 }
 
 constexpr unsigned int kOut = 0x80000000u;  // lane offset past every view: loads 0, stores drop
+
+// One output cell (x' = xp, displacement d) with range maximum m reached at
+// row ra, stored through the views of the wave's rows of V_i (ov) and
+// A_{i+1} (av).
+template <typename AT>
+__device__ __forceinline__ void emit(const DpJob& a, const RowView& ov, const RowView& av, int m,
+                                     int ra, int hval, int xp, int d, unsigned long long& best) {
+    const int n = a.n, w = a.w;
+    const int D = 2 * n - 1;
+    const int r = d + n - 1;
+    if (xp >= w || r >= D) return;
+    const bool last = a.key != nullptr;
+    if (!last) {
+        const unsigned int arow = row_off(av, r, a.a_pitch, sizeof(AT));
+        const unsigned int aval = (unsigned int)(ra < 0 ? 0 : ra);
+        if constexpr (sizeof(AT) == 1)
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)aval, av.rs, xp, (int)arow,
+                                                 kStoreScope);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)aval, av.rs, xp * 2, (int)arow,
+                                                  kStoreScope);
+    }
+    const int x = xp - d;
+    if (x < 0 || x >= w) return;
+    const int val = (m >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hval + m : -1;
+    if (last) {
+        const unsigned long long kk = pack_key(val, x, r, D);
+        best = kk > best ? kk : best;
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(val, ov.rs, x * 4, (int)row_off(ov, r, a.v_pitch, 4),
+                                              kStoreScope);
+    }
+}
 
 // Sliding maximum of the windows [j, j + 2B] of v, j = 0 .. DC-1, with the
 // smallest index reaching it (van Herk / Gil-Werman: suffix maxima and prefix
@@ -360,11 +377,11 @@ __device__ __forceinline__ unsigned long long fixed_interior(const DpJob& a, int
         const int val = m[j] >= 0 ? hv[j] + m[j] : -1;
         const unsigned int row = (unsigned int)(r0 - B + ia[j]);  // d' + n - 1 of the maximum
         if constexpr (sizeof(AT) == 1)
-            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)row, ar, xp, (int)(j * ap), 0);
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)row, ar, xp, (int)(j * ap), kStoreScope);
         else
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)row, ar, xp * 2, (int)(j * ap), 0);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)row, ar, xp * 2, (int)(j * ap), kStoreScope);
         __builtin_amdgcn_raw_buffer_store_b32(val, orr, (int)(diag + (DC - 1 - j) * 4),
-                                              (int)(j * op), 0);
+                                              (int)(j * op), kStoreScope);
     }
     return best;
 }
@@ -434,13 +451,13 @@ __device__ __forceinline__ unsigned long long fixed_general(const DpJob& a, int 
             const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
             if constexpr (sizeof(AT) == 1)
                 __builtin_amdgcn_raw_buffer_store_b8(
-                    (unsigned char)av, aview.rs, (int)(cell ? (unsigned int)xp : kOut), (int)ar, 0);
+                    (unsigned char)av, aview.rs, (int)(cell ? (unsigned int)xp : kOut), (int)ar, kStoreScope);
             else
                 __builtin_amdgcn_raw_buffer_store_b16(
                     (unsigned short)av, aview.rs, (int)(cell ? (unsigned int)xp * 2u : kOut),
-                    (int)ar, 0);
+                    (int)ar, kStoreScope);
             __builtin_amdgcn_raw_buffer_store_b32(
-                val, oview.rs, (int)(live ? (unsigned int)x * 4u : kOut), (int)vr, 0);
+                val, oview.rs, (int)(live ? (unsigned int)x * 4u : kOut), (int)vr, kStoreScope);
         }
     }
     return best;
@@ -593,9 +610,9 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
             const unsigned int off =
                 own ? (unsigned int)(row - a1v.base) * ap + (unsigned int)xs * (unsigned int)esz : kOut;
             if constexpr (sizeof(AT) == 1)
-                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, a1v.rs, (int)off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, a1v.rs, (int)off, 0, kStoreScope);
             else
-                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, a1v.rs, (int)off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, a1v.rs, (int)off, 0, kStoreScope);
         }
     }
     __syncthreads();
@@ -622,13 +639,13 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
         const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
         if constexpr (sizeof(AT) == 1)
             __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs,
-                                                 (int)(cell ? (unsigned int)xp : kOut), (int)arow, 0);
+                                                 (int)(cell ? (unsigned int)xp : kOut), (int)arow, kStoreScope);
         else
             __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs,
                                                   (int)(cell ? (unsigned int)xp * 2u : kOut),
-                                                  (int)arow, 0);
+                                                  (int)arow, kStoreScope);
         __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs,
-                                              (int)(live ? (unsigned int)x * 4u : kOut), (int)vrow, 0);
+                                              (int)(live ? (unsigned int)x * 4u : kOut), (int)vrow, kStoreScope);
     }
 }
 
@@ -662,6 +679,10 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     const int D = 2 * n - 1;
     const int jn = min(kDCGeneric, D - (d0 + n - 1));  // displacements of this wave
     const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
+    const bool last = a.key != nullptr;  // no planes to write (views unused)
+    const RowView ov = row_view(last ? a.vin : a.vout, a.v_pitch, 4, d0 + n - 1, kDCGeneric, D);
+    const RowView av = row_view(last ? a.vin : a.aout, a.a_pitch, sizeof(AT), d0 + n - 1,
+                                kDCGeneric, D);
     int hv[kDCGeneric];
 #pragma unroll
     for (int j = 0; j < kDCGeneric; ++j) hv[j] = load_h(a, xp, d0 + j);
@@ -709,7 +730,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
 #pragma unroll
         for (int j = 0; j < kDCGeneric; ++j) {
             if (j >= jn) break;
-            emit<AT>(a, m, ia + n - 1, hv[j], xp, d0 + j, best);
+            emit<AT>(a, ov, av, m, ia + n - 1, hv[j], xp, d0 + j, best);
         }
         finish(a, best, local);
         return;
@@ -780,7 +801,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
         if (j >= jn) break;
         const int m = res_v[wave][j][lane];
         const int ia = res_i[wave][j][lane];
-        emit<AT>(a, m, ia + n - 1, hv[j], xp, d0 + j, best);
+        emit<AT>(a, ov, av, m, ia + n - 1, hv[j], xp, d0 + j, best);
     }
     finish(a, best, local);
 }
