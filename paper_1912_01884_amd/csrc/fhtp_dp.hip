@@ -518,6 +518,13 @@ struct DpPairJob {
     int n, w, items_x;
 };
 
+// Masks: a thread's loads of V_{i+2} are consecutive rows of one column, so
+// the valid ones form a range of the row index; table loads are not masked
+// at all (a cell outside the image only yields a value that is never used,
+// and offsets outside a view read 0); stores are masked by ranges of the
+// row index and write nothing outside their rows.  All variable parts of an
+// offset go to the lane offset, which is what the hardware checks against
+// the view's extent.
 template <int B, typename AT>
 __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
     constexpr int RM = kPairRows + 2 * B;  // rows of V_{i+1} the workgroup needs
@@ -526,7 +533,9 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
     constexpr int NV1 = kStrip + 2 * B;
     constexpr int NV2 = kPairDC + 2 * B;
     constexpr int esz = (int)sizeof(AT);
-    __shared__ int mid[RM][64];  // V_{i+1}(X0 + lane, row m0 + q)
+    constexpr int LP = kStrip - 1;         // padding on either side of an LDS row
+    constexpr int LWP = 64 + 2 * LP;       // strip cells outside the tile land in the padding
+    __shared__ int mid[NS * kStrip][LWP];  // V_{i+1}(X0 + c, row m0 + q) at [q][LP + c]
 
     const int n = a.n, w = a.w;
     const int D = 2 * n - 1;
@@ -536,6 +545,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
     const int m0 = r0 - B;          // table row of mid[0]
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
 
     // Phase 2's H_i(x' - d, d), issued first so that the loads overlap phase 1.
     const int xp = X0 + lane;
@@ -543,72 +553,65 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
     const int r2 = r0 + wave * kPairDC;
     const int d2 = r2 - (n - 1);
     const RowView h0v = row_view(a.h0, a.h_pitch, 4, r2, kPairDC, D);
+    const unsigned int h0b = (unsigned int)(r2 - h0v.base) * hp + (unsigned int)(xp - d2) * 4u;
     int hv0[kPairDC];
 #pragma unroll
-    for (int j = 0; j < kPairDC; ++j) {
-        const int x = xp - d2 - j;
-        const bool ok = col_ok && r2 + j < D && (unsigned)x < (unsigned)w;
-        const int t = __builtin_amdgcn_raw_buffer_load_b32(
-            h0v.rs, (int)(ok ? (unsigned int)x * 4u : kOut),
-            (int)row_off(h0v, r2 + j, a.h_pitch, 4), 0);
-        hv0[j] = ok ? t : 0;
-    }
+    for (int j = 0; j < kPairDC; ++j)
+        hv0[j] = __builtin_amdgcn_raw_buffer_load_b32(h0v.rs, (int)(h0b + j * (hp - 4u)), 0, 0);
 
     // Phase 1.  Views: V_{i+2} rows [m0 - B, m0 + NS*kStrip + B), H_{i+1} rows
-    // [m0, m0 + RM), A_{i+2} rows [r0, r0 + kPairRows), each clipped to [0, D);
-    // every access below checks its row against [0, D) and the view's range.
+    // [m0, m0 + RM), A_{i+2} rows [r0, r0 + kPairRows), each clipped to [0, D).
     const RowView vv = row_view(a.vin, a.vin_pitch, 4, m0 - B, NS * kStrip + 2 * B, D);
     const RowView h1v = row_view(a.h1, a.h_pitch, 4, m0, RM, D);
     const RowView a1v = row_view(a.a1, a.a_pitch, esz, r0, kPairRows, D);
     const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
-    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
     const unsigned int ap = (unsigned int)a.a_pitch * (unsigned int)esz;
     for (int t = threadIdx.x; t < NS * SC; t += 64 * kPairWaves) {
         const int s = t / SC, c = t - s * SC;
-        const int q0 = s * kStrip;       // mid row of the strip's first displacement
-        const int rs = m0 + q0;          // its table row
+        const int q0 = s * kStrip;             // mid row of the strip's first displacement
+        const int rs = m0 + q0;                // its table row
         const int xs = X0 + rs - (n - 1) + c;  // successor column x''
         const bool xs_ok = (unsigned)xs < (unsigned)w;
+        // v[q] = V_{i+2}(x'', row rs - B + q): a cell when the row lies in
+        // [0, D) and x'' plus its displacement in [0, w)
+        const int rlo = rs - B;
+        const int qlo = max(-rlo, (n - 1) - xs - rlo);
+        const int qhi = xs_ok ? min(D - rlo, (w + n - 1) - xs - rlo) : qlo;
+        const unsigned int vb = (unsigned int)(rlo - vv.base) * vp + (unsigned int)xs * 4u;
         int v[NV1];
 #pragma unroll
         for (int q = 0; q < NV1; ++q) {
-            const int row = rs - B + q;
-            const bool ok = xs_ok && row >= 0 && row < D &&
-                            (unsigned)(xs + row - (n - 1)) < (unsigned)w;
-            const int tv = __builtin_amdgcn_raw_buffer_load_b32(
-                vv.rs, (int)(ok ? (unsigned int)(row - vv.base) * vp + (unsigned int)xs * 4u : kOut),
-                0, 0);
+            const bool ok = q >= qlo && q < qhi;
+            const int tv = __builtin_amdgcn_raw_buffer_load_b32(vv.rs, (int)(ok ? vb + q * vp : kOut),
+                                                                0, 0);
             v[q] = ok ? tv : -1;
         }
-        // H_{i+1}(x', d') of the strip's cells in the tile: x' = X0 + c - j
+        // H_{i+1}(x', d') at x' = X0 + c - j, row rs + j
+        const unsigned int hb = (unsigned int)(rs - h1v.base) * hp + (unsigned int)(X0 + c) * 4u;
         int hv[kStrip];
 #pragma unroll
-        for (int j = 0; j < kStrip; ++j) {
-            const int row = rs + j;
-            const int x1 = X0 + c - j;
-            const bool ok = (unsigned)(c - j) < 64u && q0 + j < RM && row >= 0 && row < D &&
-                            x1 < w;
-            const int tv = __builtin_amdgcn_raw_buffer_load_b32(
-                h1v.rs, (int)(ok ? (unsigned int)(row - h1v.base) * hp + (unsigned int)x1 * 4u : kOut),
-                0, 0);
-            hv[j] = ok ? tv : 0;
-        }
+        for (int j = 0; j < kStrip; ++j)
+            hv[j] = __builtin_amdgcn_raw_buffer_load_b32(h1v.rs, (int)(hb + j * (hp - 4u)), 0, 0);
         __builtin_amdgcn_sched_barrier(0);
         int m[kStrip], ia[kStrip];
         window_max<B, kStrip>(v, m, ia);
+        // cell j exists when its row lies in [0, D), x' = X0 + c - j < w and
+        // x'' lies in [0, w); it is in the tile when 0 <= c - j < 64
+        const int jlo = max(-rs, X0 + c - w + 1);
+        const int jhi = xs_ok ? D - rs : jlo;
+        int* lrow = &mid[q0][LP + c];
+        const unsigned int ab = (unsigned int)(rs - a1v.base) * ap + (unsigned int)xs * (unsigned int)esz;
 #pragma unroll
         for (int j = 0; j < kStrip; ++j) {
-            const int row = rs + j;
-            const int x1 = X0 + c - j;
-            const bool in = (unsigned)(c - j) < 64u && q0 + j < RM;
-            const bool live = in && xs_ok && row >= 0 && row < D && x1 < w;
+            const bool live = j >= jlo && j < jhi;
             const int val = live && m[j] >= 0 ? hv[j] + m[j] : -1;
-            if (in) mid[q0 + j][c - j] = val;
-            const bool own = live && row >= r0 && row < r0 + kPairRows;
+            lrow[j * (LWP - 1)] = val;
+            // back-pointer of an own row (rows outside [r0, r0 + kPairRows) fall
+            // outside the view and are dropped)
+            const bool put = xs_ok && (unsigned)(c - j) < 64u;
             const int ra = rs - B + ia[j];  // row of the maximum's d''
             const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
-            const unsigned int off =
-                own ? (unsigned int)(row - a1v.base) * ap + (unsigned int)xs * (unsigned int)esz : kOut;
+            const unsigned int off = put ? ab + j * ap : kOut;
             if constexpr (sizeof(AT) == 1)
                 __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, a1v.rs, (int)off, 0, kStoreScope);
             else
@@ -620,32 +623,33 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
     // Phase 2: step i on the LDS copy of V_{i+1}; rows outside [0, D) and
     // cells without a successor column hold -1.
     int v2[NV2];
+    const int* lcol = &mid[wave * kPairDC][LP + lane];
 #pragma unroll
-    for (int q = 0; q < NV2; ++q) v2[q] = mid[wave * kPairDC + q][lane];
+    for (int q = 0; q < NV2; ++q) v2[q] = lcol[q * LWP];
     int m2[kPairDC], ia2[kPairDC];
     window_max<B, kPairDC>(v2, m2, ia2);
     const RowView aview = row_view(a.a0, a.a_pitch, esz, r2, kPairDC, D);
     const RowView oview = row_view(a.vout, a.v_pitch, 4, r2, kPairDC, D);
+    const unsigned int op = (unsigned int)a.v_pitch * 4u;
+    // cell j: row r2 + j < D; V_i(x, d) at x = xp - d2 - j in [0, w)
+    const int jn = col_ok ? min(kPairDC, D - r2) : 0;
+    const int xj = xp - d2;  // x of cell j is xj - j
+    const unsigned int ob = (unsigned int)xj * 4u;
+    const unsigned int ab2 = (unsigned int)xp * (unsigned int)esz;
 #pragma unroll
     for (int j = 0; j < kPairDC; ++j) {
-        const int r = r2 + j;
-        const int x = xp - d2 - j;
-        const bool cell = col_ok && r < D;
-        const bool live = cell && (unsigned)x < (unsigned)w;
+        const bool cell = j < jn;
+        const bool live = cell && (unsigned)(xj - j) < (unsigned)w;
         const int val = m2[j] >= 0 ? hv0[j] + m2[j] : -1;
-        const unsigned int arow = row_off(aview, r, a.a_pitch, esz);
-        const unsigned int vrow = row_off(oview, r, a.v_pitch, 4);
         const int ra = r2 - B + ia2[j];
         const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
+        const unsigned int aoff = cell ? ab2 + j * ap : kOut;
         if constexpr (sizeof(AT) == 1)
-            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs,
-                                                 (int)(cell ? (unsigned int)xp : kOut), (int)arow, kStoreScope);
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs, (int)aoff, 0, kStoreScope);
         else
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs,
-                                                  (int)(cell ? (unsigned int)xp * 2u : kOut),
-                                                  (int)arow, kStoreScope);
-        __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs,
-                                              (int)(live ? (unsigned int)x * 4u : kOut), (int)vrow, kStoreScope);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs, (int)aoff, 0, kStoreScope);
+        __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs, (int)(live ? ob + j * (op - 4u) : kOut),
+                                              0, kStoreScope);
     }
 }
 
