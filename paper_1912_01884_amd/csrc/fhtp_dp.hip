@@ -38,6 +38,7 @@
 // batch of images of different sizes shares one launch per step instead of one
 // per image and step.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "fhtp_internal.h"
@@ -577,46 +578,61 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
         const int rlo = rs - B;
         const int qlo = max(-rlo, (n - 1) - xs - rlo);
         const int qhi = xs_ok ? min(D - rlo, (w + n - 1) - xs - rlo) : qlo;
-        const unsigned int vb = (unsigned int)(rlo - vv.base) * vp + (unsigned int)xs * 4u;
-        int v[NV1];
-#pragma unroll
-        for (int q = 0; q < NV1; ++q) {
-            const bool ok = q >= qlo && q < qhi;
-            const int tv = __builtin_amdgcn_raw_buffer_load_b32(vv.rs, (int)(ok ? vb + q * vp : kOut),
-                                                                0, 0);
-            v[q] = ok ? tv : -1;
-        }
-        // H_{i+1}(x', d') at x' = X0 + c - j, row rs + j
-        const unsigned int hb = (unsigned int)(rs - h1v.base) * hp + (unsigned int)(X0 + c) * 4u;
-        int hv[kStrip];
-#pragma unroll
-        for (int j = 0; j < kStrip; ++j)
-            hv[j] = __builtin_amdgcn_raw_buffer_load_b32(h1v.rs, (int)(hb + j * (hp - 4u)), 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        int m[kStrip], ia[kStrip];
-        window_max<B, kStrip>(v, m, ia);
         // cell j exists when its row lies in [0, D), x' = X0 + c - j < w and
         // x'' lies in [0, w); it is in the tile when 0 <= c - j < 64
         const int jlo = max(-rs, X0 + c - w + 1);
         const int jhi = xs_ok ? D - rs : jlo;
-        int* lrow = &mid[q0][LP + c];
+        const unsigned int vb = (unsigned int)(rlo - vv.base) * vp + (unsigned int)xs * 4u;
+        const unsigned int hb = (unsigned int)(rs - h1v.base) * hp + (unsigned int)(X0 + c) * 4u;
         const unsigned int ab = (unsigned int)(rs - a1v.base) * ap + (unsigned int)xs * (unsigned int)esz;
+        int* lrow = &mid[q0][LP + c];
+        // A wave whose every load and cell is valid takes the unmasked copy.
+        const bool inner = qlo <= 0 && qhi >= NV1 && jlo <= 0 && jhi >= kStrip;
+        auto strip = [&](auto inner_tag) {
+            constexpr bool INNER = decltype(inner_tag)::value;
+            int v[NV1];
 #pragma unroll
-        for (int j = 0; j < kStrip; ++j) {
-            const bool live = j >= jlo && j < jhi;
-            const int val = live && m[j] >= 0 ? hv[j] + m[j] : -1;
-            lrow[j * (LWP - 1)] = val;
-            // back-pointer of an own row (rows outside [r0, r0 + kPairRows) fall
-            // outside the view and are dropped)
-            const bool put = xs_ok && (unsigned)(c - j) < 64u;
-            const int ra = rs - B + ia[j];  // row of the maximum's d''
-            const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
-            const unsigned int off = put ? ab + j * ap : kOut;
-            if constexpr (sizeof(AT) == 1)
-                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, a1v.rs, (int)off, 0, kStoreScope);
-            else
-                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, a1v.rs, (int)off, 0, kStoreScope);
-        }
+            for (int q = 0; q < NV1; ++q) {
+                if constexpr (INNER) {
+                    v[q] = __builtin_amdgcn_raw_buffer_load_b32(vv.rs, (int)(vb + q * vp), 0, 0);
+                } else {
+                    const bool ok = q >= qlo && q < qhi;
+                    const int tv = __builtin_amdgcn_raw_buffer_load_b32(
+                        vv.rs, (int)(ok ? vb + q * vp : kOut), 0, 0);
+                    v[q] = ok ? tv : -1;
+                }
+            }
+            // H_{i+1}(x', d') at x' = X0 + c - j, row rs + j
+            int hv[kStrip];
+#pragma unroll
+            for (int j = 0; j < kStrip; ++j)
+                hv[j] = __builtin_amdgcn_raw_buffer_load_b32(h1v.rs, (int)(hb + j * (hp - 4u)), 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            int m[kStrip], ia[kStrip];
+            window_max<B, kStrip>(v, m, ia);
+#pragma unroll
+            for (int j = 0; j < kStrip; ++j) {
+                const bool live = INNER || (j >= jlo && j < jhi);
+                const int val = live && m[j] >= 0 ? hv[j] + m[j] : -1;
+                lrow[j * (LWP - 1)] = val;
+                // back-pointer of an own row (rows outside [r0, r0 + kPairRows)
+                // fall outside the view and are dropped)
+                const bool put = (INNER || xs_ok) && (unsigned)(c - j) < 64u;
+                const int ra = rs - B + ia[j];  // row of the maximum's d''
+                const unsigned int av = (unsigned int)(INNER || ra >= 0 ? ra : 0);
+                const unsigned int off = put ? ab + j * ap : kOut;
+                if constexpr (sizeof(AT) == 1)
+                    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, a1v.rs, (int)off, 0,
+                                                         kStoreScope);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, a1v.rs, (int)off, 0,
+                                                          kStoreScope);
+            }
+        };
+        if (__builtin_amdgcn_ballot_w64(!inner) == 0)
+            strip(std::true_type{});
+        else
+            strip(std::false_type{});
     }
     __syncthreads();
 
@@ -836,6 +852,67 @@ __global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
     finish(a, best, local);
 }
 
+// Three bands of the walk in one memory round trip, for windows of at most
+// 2*kMaxFixedB + 1 displacements: with x_i and d_i known, read
+// A_{i+1}(x_{i+1}, d_i), every candidate A_{i+2}(x_{i+1} + d', d') for d' in
+// the window of d_i, and every candidate A_{i+3} for d'' in the windows of
+// those d' (U loads per lane cover the pairs).  Returns false when a link
+// leaves the image (the caller reports no polyline).
+template <typename AT, int U>
+__device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, int& r, int& i) {
+    const int n = a.n, w = a.w, D = 2 * n - 1;
+    const int B = a.bound, L1 = 2 * B + 1;
+    const unsigned int pitch = (unsigned int)a.a_pitch;
+    const int xn = x + r - (n - 1);
+    if (xn < 0 || xn >= w || r < 0 || r >= D) return false;
+    const AT* P1 = static_cast<const AT*>(a.a_base) + (size_t)(i - 1) * a.a_plane;  // A_{i+1}
+    const AT* P2 = P1 + a.a_plane;                                                  // A_{i+2}
+    const AT* P3 = P2 + a.a_plane;                                                  // A_{i+3}
+    const int rn = P1[(unsigned int)r * pitch + (unsigned int)xn];
+    int s1;
+    {
+        const int c1 = r - B + lane;
+        const int x2 = xn + c1 - (n - 1);
+        const bool ok = lane < L1 && c1 >= 0 && c1 < D && x2 >= 0 && x2 < w;
+        const int v = P2[ok ? (unsigned int)c1 * pitch + (unsigned int)x2 : 0u];
+        s1 = ok ? v : 0;
+    }
+    int s2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int q = lane + 64 * u;
+        const int l1 = q / L1, l2 = q - l1 * L1;
+        const int c1 = r - B + l1, c2 = c1 - B + l2;
+        const int x2 = xn + c1 - (n - 1), x3 = x2 + c2 - (n - 1);
+        const bool ok = q < L1 * L1 && c1 >= 0 && c1 < D && c2 >= 0 && c2 < D && x2 >= 0 && x2 < w &&
+                        x3 >= 0 && x3 < w;
+        const int v = P3[ok ? (unsigned int)c2 * pitch + (unsigned int)x3 : 0u];
+        s2[u] = ok ? v : 0;
+    }
+    const int l1 = rn - (r - B);
+    if ((unsigned)l1 >= (unsigned)L1 || rn >= D) return false;
+    if (lane == 0) a.xs[i + 1] = xn;
+    const int xnn = xn + rn - (n - 1);
+    if (xnn < 0 || xnn >= w) return false;
+    const int r2 = __shfl(s1, l1, 64);
+    const int l2 = r2 - (rn - B);
+    if ((unsigned)l2 >= (unsigned)L1 || r2 < 0 || r2 >= D) return false;
+    if (lane == 0) a.xs[i + 2] = xnn;
+    const int x3 = xnn + r2 - (n - 1);
+    if (x3 < 0 || x3 >= w) return false;
+    const int q = l1 * L1 + l2;
+    const int slot = q >> 6;
+    int mine = s2[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) mine = slot == u ? s2[u] : mine;
+    const int r3 = __shfl(mine, q & 63, 64);
+    if (lane == 0) a.xs[i + 3] = x3;
+    x = x3;
+    r = r3;
+    i += 3;
+    return true;
+}
+
 // Walk of eq. (5), one wave per image: reduce the workgroup keys of the last
 // step, then follow the back-pointers.  The walk is a chain of dependent
 // loads, so every load is unconditional (clamped index, result masked) and
@@ -892,13 +969,26 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
         if (lane == 0) a.xs[1] = x1;
         x = x1;
         r = r1;
-        // Later successors from the stored planes, two bands per round trip:
-        // with link i known, read A_{i+1}(x_{i+1}, d_i) and, for every possible
-        // d_{i+1} (lane-strided), A_{i+2}(x_{i+1} + d_{i+1}, d_{i+1}).
+        // Later successors from the stored planes: three bands per round trip
+        // for narrow fixed windows (walk_three), else two: with link i known,
+        // read A_{i+1}(x_{i+1}, d_i) and, for every possible d_{i+1}
+        // (lane-strided), A_{i+2}(x_{i+1} + d_{i+1}, d_{i+1}).
         const AT* A = static_cast<const AT*>(a.a_base);
         const unsigned int pitch = (unsigned int)a.a_pitch;
+        const int L1 = 2 * a.bound + 1;
+        const bool narrow = !a.full && a.win == nullptr && a.bound <= kMaxFixedB;
         int i = 1;
         while (i + 1 < k) {
+            if (narrow && i + 3 < k) {
+                const bool ok = L1 * L1 <= 256   ? walk_three<AT, 4>(a, lane, x, r, i)
+                                : L1 * L1 <= 576 ? walk_three<AT, 9>(a, lane, x, r, i)
+                                                 : walk_three<AT, 18>(a, lane, x, r, i);
+                if (!ok) {
+                    if (lane == 0) *a.score = -1;
+                    return;
+                }
+                continue;
+            }
             const int xn = x + r - (n - 1);
             if (xn < 0 || xn >= w || r < 0 || r >= D) {
                 if (lane == 0) *a.score = -1;
