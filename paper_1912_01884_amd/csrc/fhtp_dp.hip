@@ -388,78 +388,91 @@ __device__ __forceinline__ unsigned long long fixed_interior(const DpJob& a, int
 }
 
 // One wave of a mode-0 step with the window [d - B, d + B] fixed at compile
-// time, anywhere in the planes: every access masked (cells outside the image
-// or the planes, pinned columns).  All loads first (the window column of
-// V_{i+1} and the H_i cells), then the sliding maximum, then the cells.
+// time, anywhere in the planes (cells outside the image or the planes,
+// pinned columns).  All loads first (the window column of V_{i+1} and the H_i
+// cells), then the sliding maximum, then the cells.  A thread's V loads are
+// consecutive rows of one column, so the valid ones form a range of the row
+// index; H loads are not masked (a cell outside the image only yields a value
+// that is never used, and offsets outside a view read 0); stores are masked
+// by ranges and every variable offset part sits in the lane offset, which the
+// hardware checks against the view's extent.
 template <int B, int DC, typename AT>
 __device__ __forceinline__ unsigned long long fixed_general(const DpJob& a, int X0, int r0,
                                                             int d0) {
     constexpr int NV = DC + 2 * B;
+    constexpr int esz = (int)sizeof(AT);
     const int n = a.n, w = a.w;
     const int D = 2 * n - 1;
     const int xp = X0 + (int)(threadIdx.x & 63);
-    const bool col_ok = (unsigned)xp < (unsigned)w;
+    const bool col_ok = xp < w;
 
     // H_i(x' - d, d), d = d0 + j: rows r0 + j, column x' - d.
     const RowView hview = row_view(a.htab, a.h_pitch, 4, r0, DC, D);
+    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
+    const unsigned int hb = (unsigned int)(r0 - hview.base) * hp + (unsigned int)(xp - d0) * 4u;
     int hv[DC];
 #pragma unroll
-    for (int j = 0; j < DC; ++j) {
-        const int x = xp - d0 - j;
-        const bool ok = col_ok && r0 + j < D && (unsigned)x < (unsigned)w;
-        const int t = __builtin_amdgcn_raw_buffer_load_b32(
-            hview.rs, (int)(ok ? (unsigned int)x * 4u : kOut),
-            (int)row_off(hview, r0 + j, a.h_pitch, 4), 0);
-        hv[j] = ok ? t : 0;
-    }
-    // V_{i+1}(x', d'), d' = d0 - B + j: rows r0 - B + j, column x'.
+    for (int j = 0; j < DC; ++j)
+        hv[j] = __builtin_amdgcn_raw_buffer_load_b32(hview.rs, (int)(hb + j * (hp - 4u)), 0, 0);
+    // V_{i+1}(x', d'), d' = d0 - B + q: rows r0 - B + q, column x'; a cell when
+    // x' passes the pin, the row lies in [0, D) and x' + d' in [tlo, tlo + tlen).
     const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
     const bool xin = (unsigned)(xp - mk.xlo) < (unsigned)mk.xlen;
-    const int tx = xp + d0 - B - mk.tlo;  // x' + d' - tlo at j = 0
-    const RowView vview = row_view(a.vin, a.vin_pitch, 4, r0 - B, NV, D);
+    const int rlo = r0 - B;
+    const int qlo = max(-rlo, mk.tlo - xp - rlo + (n - 1));
+    const int qhi = xin ? min(D - rlo, mk.tlo + mk.tlen - xp - rlo + (n - 1)) : qlo;
+    const RowView vview = row_view(a.vin, a.vin_pitch, 4, rlo, NV, D);
+    const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
+    const unsigned int vb = (unsigned int)(rlo - vview.base) * vp + (unsigned int)xp * 4u;
     int v[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int row = r0 - B + j;
-        const bool ok = xin && row >= 0 && row < D && (unsigned)(tx + j) < (unsigned)mk.tlen;
-        const int t = __builtin_amdgcn_raw_buffer_load_b32(
-            vview.rs, (int)(ok ? (unsigned int)xp * 4u : kOut),
-            (int)row_off(vview, row, a.vin_pitch, 4), 0);
-        v[j] = ok ? t : -1;
+    for (int q = 0; q < NV; ++q) {
+        const bool ok = q >= qlo && q < qhi;
+        const int t = __builtin_amdgcn_raw_buffer_load_b32(vview.rs, (int)(ok ? vb + q * vp : kOut),
+                                                           0, 0);
+        v[q] = ok ? t : -1;
     }
     __builtin_amdgcn_sched_barrier(0);
     int m[DC], ia[DC];
     window_max<B, DC>(v, m, ia);
 
+    // cell j: row r0 + j < D; V_i(x, d) at x = x' - d0 - j in [0, w)
+    const int jn = col_ok ? min(DC, D - r0) : 0;
+    const int xj = xp - d0;  // x of cell j is xj - j
     const bool last = a.key != nullptr;
-    const RowView aview = row_view(last ? a.vin : a.aout, a.a_pitch, sizeof(AT), r0, DC, D);
-    const RowView oview = row_view(last ? a.vin : a.vout, a.v_pitch, 4, r0, DC, D);
     unsigned long long best = 0;
+    if (last) {
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+            const int x = xj - j;
+            const bool live = j < jn && (unsigned)x < (unsigned)w;
+            const int val = (m[j] >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hv[j] + m[j] : -1;
+            const unsigned long long kk = live ? pack_key(val, x, r0 + j, D) : 0ull;
+            best = kk > best ? kk : best;
+        }
+        return best;
+    }
+    const RowView aview = row_view(a.aout, a.a_pitch, esz, r0, DC, D);
+    const RowView oview = row_view(a.vout, a.v_pitch, 4, r0, DC, D);
+    const unsigned int ap = (unsigned int)a.a_pitch * (unsigned int)esz;
+    const unsigned int op = (unsigned int)a.v_pitch * 4u;
+    const unsigned int ab = (unsigned int)(r0 - aview.base) * ap + (unsigned int)xp * (unsigned int)esz;
+    const unsigned int ob = (unsigned int)(r0 - oview.base) * op + (unsigned int)xj * 4u;
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
-        const int ra = r0 - B + ia[j];  // row of the maximum's d'
-        const int r = r0 + j;
-        const int x = xp - d0 - j;
-        const bool cell = col_ok && r < D;
+        const int x = xj - j;
+        const bool cell = j < jn;
         const bool live = cell && (unsigned)x < (unsigned)w;
         const int val = (m[j] >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hv[j] + m[j] : -1;
-        if (last) {
-            const unsigned long long kk = live ? pack_key(val, x, r, D) : 0ull;
-            best = kk > best ? kk : best;
-        } else {
-            const unsigned int ar = row_off(aview, r, a.a_pitch, sizeof(AT));
-            const unsigned int vr = row_off(oview, r, a.v_pitch, 4);
-            const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
-            if constexpr (sizeof(AT) == 1)
-                __builtin_amdgcn_raw_buffer_store_b8(
-                    (unsigned char)av, aview.rs, (int)(cell ? (unsigned int)xp : kOut), (int)ar, kStoreScope);
-            else
-                __builtin_amdgcn_raw_buffer_store_b16(
-                    (unsigned short)av, aview.rs, (int)(cell ? (unsigned int)xp * 2u : kOut),
-                    (int)ar, kStoreScope);
-            __builtin_amdgcn_raw_buffer_store_b32(
-                val, oview.rs, (int)(live ? (unsigned int)x * 4u : kOut), (int)vr, kStoreScope);
-        }
+        const int ra = rlo + ia[j];  // row of the maximum's d'
+        const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
+        const unsigned int aoff = cell ? ab + j * ap : kOut;
+        if constexpr (sizeof(AT) == 1)
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs, (int)aoff, 0, kStoreScope);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs, (int)aoff, 0, kStoreScope);
+        __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs, (int)(live ? ob + j * (op - 4u) : kOut), 0,
+                                              kStoreScope);
     }
     return best;
 }
@@ -853,11 +866,14 @@ __global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
 }
 
 // Three bands of the walk in one memory round trip, for windows of at most
-// 2*kMaxFixedB + 1 displacements: with x_i and d_i known, read
-// A_{i+1}(x_{i+1}, d_i), every candidate A_{i+2}(x_{i+1} + d', d') for d' in
-// the window of d_i, and every candidate A_{i+3} for d'' in the windows of
-// those d' (U loads per lane cover the pairs).  Returns false when a link
-// leaves the image (the caller reports no polyline).
+// 31 displacements: with x_i and d_i known, read A_{i+1}(x_{i+1}, d_i), every
+// candidate A_{i+2}(x_{i+1} + d', d') for d' in the window of d_i (one per
+// lane), and every candidate A_{i+3} for d'' in the window of each d' (lanes
+// 0-31 take the even d' of the window, lanes 32-63 the odd ones, U loads per
+// lane).  Candidate indices are clamped into the planes rather than masked:
+// the candidate that is finally selected is always inside, and what the
+// others read is never used.  Returns false when a link leaves the image (the
+// caller reports no polyline).
 template <typename AT, int U>
 __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, int& r, int& i) {
     const int n = a.n, w = a.w, D = 2 * n - 1;
@@ -871,23 +887,18 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
     const int rn = P1[(unsigned int)r * pitch + (unsigned int)xn];
     int s1;
     {
-        const int c1 = r - B + lane;
-        const int x2 = xn + c1 - (n - 1);
-        const bool ok = lane < L1 && c1 >= 0 && c1 < D && x2 >= 0 && x2 < w;
-        const int v = P2[ok ? (unsigned int)c1 * pitch + (unsigned int)x2 : 0u];
-        s1 = ok ? v : 0;
+        const int c1 = min(max(r - B + lane, 0), D - 1);
+        const int x2 = min(max(xn + c1 - (n - 1), 0), w - 1);
+        s1 = P2[(unsigned int)c1 * pitch + (unsigned int)x2];
     }
+    const int l2 = lane & 31;
     int s2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int q = lane + 64 * u;
-        const int l1 = q / L1, l2 = q - l1 * L1;
-        const int c1 = r - B + l1, c2 = c1 - B + l2;
-        const int x2 = xn + c1 - (n - 1), x3 = x2 + c2 - (n - 1);
-        const bool ok = q < L1 * L1 && c1 >= 0 && c1 < D && c2 >= 0 && c2 < D && x2 >= 0 && x2 < w &&
-                        x3 >= 0 && x3 < w;
-        const int v = P3[ok ? (unsigned int)c2 * pitch + (unsigned int)x3 : 0u];
-        s2[u] = ok ? v : 0;
+        const int c1 = r - B + 2 * u + (lane >> 5);
+        const int c2 = min(max(c1 - B + l2, 0), D - 1);
+        const int x3 = min(max(xn + c1 + c2 - 2 * (n - 1), 0), w - 1);
+        s2[u] = P3[(unsigned int)c2 * pitch + (unsigned int)x3];
     }
     const int l1 = rn - (r - B);
     if ((unsigned)l1 >= (unsigned)L1 || rn >= D) return false;
@@ -895,17 +906,16 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
     const int xnn = xn + rn - (n - 1);
     if (xnn < 0 || xnn >= w) return false;
     const int r2 = __shfl(s1, l1, 64);
-    const int l2 = r2 - (rn - B);
-    if ((unsigned)l2 >= (unsigned)L1 || r2 < 0 || r2 >= D) return false;
+    const int l2s = r2 - (rn - B);
+    if ((unsigned)l2s >= (unsigned)L1 || r2 < 0 || r2 >= D) return false;
     if (lane == 0) a.xs[i + 2] = xnn;
     const int x3 = xnn + r2 - (n - 1);
     if (x3 < 0 || x3 >= w) return false;
-    const int q = l1 * L1 + l2;
-    const int slot = q >> 6;
+    const int slot = l1 >> 1;
     int mine = s2[0];
 #pragma unroll
     for (int u = 1; u < U; ++u) mine = slot == u ? s2[u] : mine;
-    const int r3 = __shfl(mine, q & 63, 64);
+    const int r3 = __shfl(mine, ((l1 & 1) << 5) | l2s, 64);
     if (lane == 0) a.xs[i + 3] = x3;
     x = x3;
     r = r3;
@@ -970,19 +980,22 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
         x = x1;
         r = r1;
         // Later successors from the stored planes: three bands per round trip
-        // for narrow fixed windows (walk_three), else two: with link i known,
+        // for windows of at most 31 displacements (walk_three), else two: with
+        // link i known,
         // read A_{i+1}(x_{i+1}, d_i) and, for every possible d_{i+1}
         // (lane-strided), A_{i+2}(x_{i+1} + d_{i+1}, d_{i+1}).
         const AT* A = static_cast<const AT*>(a.a_base);
         const unsigned int pitch = (unsigned int)a.a_pitch;
         const int L1 = 2 * a.bound + 1;
-        const bool narrow = !a.full && a.win == nullptr && a.bound <= kMaxFixedB;
+        const bool narrow = !a.full && a.win == nullptr && L1 <= 31;
         int i = 1;
         while (i + 1 < k) {
             if (narrow && i + 3 < k) {
-                const bool ok = L1 * L1 <= 256   ? walk_three<AT, 4>(a, lane, x, r, i)
-                                : L1 * L1 <= 576 ? walk_three<AT, 9>(a, lane, x, r, i)
-                                                 : walk_three<AT, 18>(a, lane, x, r, i);
+                const bool ok = L1 <= 7    ? walk_three<AT, 4>(a, lane, x, r, i)
+                                : L1 <= 11 ? walk_three<AT, 6>(a, lane, x, r, i)
+                                : L1 <= 17 ? walk_three<AT, 9>(a, lane, x, r, i)
+                                : L1 <= 23 ? walk_three<AT, 12>(a, lane, x, r, i)
+                                           : walk_three<AT, 16>(a, lane, x, r, i);
                 if (!ok) {
                     if (lane == 0) *a.score = -1;
                     return;
