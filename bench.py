@@ -270,20 +270,19 @@ def main():
     torch.cuda.synchronize()
     ms_eager = time_events(step, args.steps, stream)
 
-    # The same step captured once in a HIP graph and replayed: one launch per
-    # step instead of one per kernel.
-    graph = torch.cuda.CUDAGraph()
-    cap = torch.cuda.Stream(dev)
-    cap.wait_stream(stream)
-    with torch.cuda.stream(cap):
-        with torch.cuda.graph(graph, stream=cap):
-            fhtp.detect_polyline(img, k, bend=B, ws=ws, score=score, xs=xs, stream=cap)
-    stream.wait_stream(cap)
+    # The same detection recorded once as a HIP graph by the library's plan
+    # calls (fhtp_plan_create / _capture) and replayed with fhtp_plan_launch:
+    # one graph launch per step instead of one launch per kernel.
+    plan = fhtp.Plan([img], [k], bends=[B], scores=[score], xss=[xs])
+
+    def replay():
+        plan.launch(stream)
+
     for _ in range(args.warmup):
-        graph.replay()
+        replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms_graph = time_events(graph.replay, args.steps, stream)
+    ms_graph = time_events(replay, args.steps, stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = max(ms_graph, 1e-9)
@@ -331,7 +330,7 @@ def main():
         "images_per_s": round(1e3 / ms_per_step, 2),
         "hbm_gbps_model": round(model["total"] / (ms_per_step * 1e-3) / 1e9, 1),
         "model_bytes": model,
-        "launch": "hip graph replay of one detect_polyline call",
+        "launch": "fhtp_plan_launch: hip graph replay of one detection",
         "eager_ms_per_step": round(ms_eager, 4),
         "phase_ms": {"fht_bands": round(ms_fht, 4), "polyline_dp": round(ms_dp, 4)},
         "roofline": {"bound": "hbm", "kernel": "fht_reg_kernel",

@@ -229,6 +229,39 @@ typedef struct {
 int fhtp_batch_workspace_bytes(const fhtp_job* jobs, int count, size_t* bytes);
 int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Plans: a fixed set of detections (one job or a batch, as fhtp_detect_batch
+ * takes them) recorded once as a HIP graph and replayed.  The FHT and the DP
+ * of Sections 2.1-2.3 and the backtrace of eq. (5) are a chain of a few dozen
+ * dependent launches; a replay submits them as one graph launch.  Results are
+ * bit-identical to fhtp_detect_batch on the same jobs.
+ *
+ * fhtp_plan_create: validates the jobs as fhtp_detect_batch does (same error
+ *   codes; nothing is created on error) and copies the descriptors.  The
+ *   device buffers they name and `ws` (fhtp_batch_workspace_bytes bytes) are
+ *   borrowed: they must stay allocated while the plan exists.  Their contents
+ *   may change between launches; every launch reads the images afresh.  The
+ *   plan belongs to the current device.
+ * fhtp_plan_capture: records the plan's launches into a graph on a stream
+ *   the library creates and destroys for the purpose, and instantiates it.
+ *   Host call; enqueues nothing.  Calling it again re-records the graph.
+ *   FHTP_ERR_HIP if capture or instantiation fails (the plan then stays
+ *   usable uncaptured).
+ * fhtp_plan_launch: replays the graph on `stream` (a stream of the plan's
+ *   device) or, if the plan has not been captured, enqueues the launches
+ *   directly; asynchronous.  Launches of one plan share `ws`, so two of them
+ *   must not run at the same time (on different streams).
+ * fhtp_plan_destroy: frees the plan and its graph (host call).  The caller
+ *   first makes sure that no launch of the plan is still running.  A null
+ *   plan is accepted.
+ * ------------------------------------------------------------------------- */
+typedef struct fhtp_plan_s* fhtp_plan;
+
+int fhtp_plan_create(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, fhtp_plan* plan);
+int fhtp_plan_capture(fhtp_plan plan);
+int fhtp_plan_launch(fhtp_plan plan, void* stream);
+int fhtp_plan_destroy(fhtp_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -506,6 +507,119 @@ int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes
     if (rc_join == FHTP_OK)
         rc_join = hip_status(hipStreamWaitEvent(s, ax->join, 0), "detect_batch/join");
     return rc_tall != FHTP_OK ? rc_tall : rc_rest != FHTP_OK ? rc_rest : rc_join;
+}
+
+}  // extern "C"
+
+// A plan: the jobs of one fhtp_detect_batch call, their workspace, and the
+// graph that records the call.
+struct fhtp_plan_s {
+    std::vector<fhtp_job> jobs;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void release_graph(fhtp_plan_s* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+// Runs f with the plan's device current, restoring the caller's device.
+template <typename F>
+int on_device(int device, const char* what, F&& f) {
+    int prev = 0;
+    int rc = hip_status(hipGetDevice(&prev), what);
+    if (rc != FHTP_OK) return rc;
+    if (prev != device) {
+        rc = hip_status(hipSetDevice(device), what);
+        if (rc != FHTP_OK) return rc;
+    }
+    rc = f();
+    if (prev != device) (void)hipSetDevice(prev);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fhtp_plan_create(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, fhtp_plan* out) {
+    if (!out) return FHTP_ERR_NULL;
+    std::vector<BatchEntry> plan_v;
+    size_t total = 0;
+    int rc = plan_batch(jobs, count, &plan_v, &total);
+    if (rc != FHTP_OK) return rc;
+    if (count > 0) {
+        rc = check_ws(ws, ws_bytes, total);
+        if (rc != FHTP_OK) return rc;
+    }
+    auto* p = new (std::nothrow) fhtp_plan_s;
+    if (!p) return FHTP_ERR_HIP;
+    p->jobs.assign(jobs, jobs + count);
+    p->ws = ws;
+    p->ws_bytes = ws_bytes;
+    rc = hip_status(hipGetDevice(&p->device), "plan_create");
+    if (rc != FHTP_OK) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return FHTP_OK;
+}
+
+int fhtp_plan_capture(fhtp_plan p) {
+    if (!p) return FHTP_ERR_NULL;
+    return on_device(p->device, "plan_capture", [&]() -> int {
+        release_graph(p);
+        if (p->jobs.empty()) return FHTP_OK;  // nothing to record: launches enqueue nothing
+        hipStream_t cs = nullptr;
+        int rc = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "plan_capture");
+        if (rc != FHTP_OK) return rc;
+        // the batch's second stream must exist before the capture opens
+        (void)aux_for_current_device(cs);
+        rc = hip_status(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "plan_capture");
+        if (rc == FHTP_OK) {
+            const int rc_run =
+                fhtp_detect_batch(p->jobs.data(), (int)p->jobs.size(), p->ws, p->ws_bytes, cs);
+            hipGraph_t g = nullptr;
+            const int rc_end = hip_status(hipStreamEndCapture(cs, &g), "plan_capture/end");
+            rc = rc_run != FHTP_OK ? rc_run : rc_end;
+            if (rc == FHTP_OK) {
+                p->graph = g;
+                rc = hip_status(hipGraphInstantiateWithFlags(&p->exec, g, 0), "plan_capture/instantiate");
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+            if (rc != FHTP_OK) release_graph(p);
+        }
+        (void)hipStreamDestroy(cs);
+        return rc;
+    });
+}
+
+int fhtp_plan_launch(fhtp_plan p, void* stream) {
+    if (!p) return FHTP_ERR_NULL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!p->exec)
+        return fhtp_detect_batch(p->jobs.data(), (int)p->jobs.size(), p->ws, p->ws_bytes, s);
+    return hip_status(hipGraphLaunch(p->exec, s), "plan_launch");
+}
+
+int fhtp_plan_destroy(fhtp_plan p) {
+    if (!p) return FHTP_OK;
+    const int rc = on_device(p->device, "plan_destroy", [&]() -> int {
+        release_graph(p);
+        return FHTP_OK;
+    });
+    delete p;
+    return rc;
 }
 
 }  // extern "C"

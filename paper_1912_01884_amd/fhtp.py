@@ -35,7 +35,8 @@ EXPORTED = (
     "fhtp_fht_workspace_bytes", "fhtp_fht_bands", "fhtp_dp_workspace_bytes", "fhtp_polyline_dp",
     "fhtp_detect_workspace_bytes", "fhtp_detect_polyline", "fhtp_batch_workspace_bytes",
     "fhtp_detect_batch", "fhtp_detect_ex_workspace_bytes", "fhtp_detect_polyline_ex",
-    "fhtp_prepare_image",
+    "fhtp_prepare_image", "fhtp_plan_create", "fhtp_plan_capture", "fhtp_plan_launch",
+    "fhtp_plan_destroy",
 )
 
 
@@ -113,6 +114,10 @@ def lib() -> C.CDLL:
     L.fhtp_detect_ex_workspace_bytes.argtypes = [i32, i32, i32, i32, Bend, optp, szp]
     L.fhtp_detect_polyline_ex.argtypes = [vp, i32, i32, i32, i32, Bend, optp, vp, sz, vp, vp, vp]
     L.fhtp_prepare_image.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+    L.fhtp_plan_create.argtypes = [C.POINTER(Job), i32, vp, sz, C.POINTER(vp)]
+    L.fhtp_plan_capture.argtypes = [vp]
+    L.fhtp_plan_launch.argtypes = [vp, vp]
+    L.fhtp_plan_destroy.argtypes = [vp]
     for name in EXPORTED:
         if name not in ("fhtp_strerror", "fhtp_last_error_detail", "fhtp_version"):
             getattr(L, name).restype = C.c_int
@@ -340,3 +345,51 @@ def detect_batch(images, ks, bends=None, gammas=None, ws=None, scores=None, xss=
     rc = lib().fhtp_detect_batch(arr, len(jobs), _ptr(ws_t), ws_n, _stream_ptr(stream))
     _check(rc, "detect_batch")
     return keep
+
+
+class Plan:
+    """A fixed set of detections recorded once as a HIP graph and replayed.
+
+    Wraps fhtp_plan_create / fhtp_plan_capture / fhtp_plan_launch /
+    fhtp_plan_destroy.  The images, outputs and workspace are borrowed for the
+    plan's lifetime (the plan keeps references to the tensors); refill the
+    images in place between launches.  results[q] is the (score, xs) pair of
+    image q, valid once the launch's stream has been synchronised.
+    """
+
+    def __init__(self, images, ks, bends=None, gammas=None, ws=None, scores=None, xss=None,
+                 capture=True):
+        if len(images) == 0:
+            raise ValueError("a plan needs at least one image")
+        jobs, keep = make_jobs(images, ks, bends, gammas, scores, xss)
+        nbytes = batch_workspace_bytes(jobs)
+        ws_t, ws_n = _ws(nbytes, images[0].device, ws)
+        arr = (Job * len(jobs))(*jobs)
+        h = C.c_void_p()
+        _check(lib().fhtp_plan_create(arr, len(jobs), _ptr(ws_t), ws_n, C.byref(h)), "plan_create")
+        self._h = h
+        self._keep = (list(images), ws_t, keep)
+        self.results = keep
+        if capture:
+            self.capture()
+
+    def capture(self) -> None:
+        _check(lib().fhtp_plan_capture(self._h), "plan_capture")
+
+    def launch(self, stream=None) -> None:
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        _check(lib().fhtp_plan_launch(self._h, _stream_ptr(stream)), "plan_launch")
+
+    def destroy(self) -> None:
+        if self._h is not None:
+            _check(lib().fhtp_plan_destroy(self._h), "plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None and _lib is not None:
+                _lib.fhtp_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass

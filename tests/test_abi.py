@@ -177,6 +177,28 @@ def test_batch_rejects_any_invalid_job_before_launch():
     assert L.fhtp_detect_batch(arr, 1, None, 1 << 30, None) == fhtp.ERR_NULL
 
 
+def test_plan_create_validates_like_batch():
+    """fhtp_plan_create rejects what fhtp_detect_batch rejects, before any HIP call."""
+    L = fhtp.lib()
+    good = _job(64, 64, 4)
+    h = C.c_void_p()
+    for bad, code in [(_job(12, 8, 4), fhtp.ERR_DIMS), (_job(64, 64, 4, dtype=3), fhtp.ERR_DTYPE),
+                      (_job(64, 64, 4, bend=fhtp.Bend(0, -1, 0.0)), fhtp.ERR_BEND),
+                      (_job(64, 64, 4, img=None), fhtp.ERR_NULL)]:
+        arr = (fhtp.Job * 2)(good, bad)
+        assert L.fhtp_plan_create(arr, 2, C.c_void_p(256), 1 << 40, C.byref(h)) == code
+        assert h.value is None
+    arr = (fhtp.Job * 1)(good)
+    assert L.fhtp_plan_create(arr, 1, C.c_void_p(256), 16, C.byref(h)) == fhtp.ERR_WORKSPACE
+    assert L.fhtp_plan_create(arr, 1, None, 1 << 30, C.byref(h)) == fhtp.ERR_NULL
+    assert L.fhtp_plan_create(arr, 1, C.c_void_p(256), 1 << 30, None) == fhtp.ERR_NULL
+    assert h.value is None
+    # a null plan: nothing to capture or launch, destroying it is a no-op
+    assert L.fhtp_plan_capture(None) == fhtp.ERR_NULL
+    assert L.fhtp_plan_launch(None, None) == fhtp.ERR_NULL
+    assert L.fhtp_plan_destroy(None) == 0
+
+
 def test_detect_ex_validation_matches_oracle(orc):
     """Option and point errors agree with the oracle's, and nothing is launched."""
     L = fhtp.lib()

@@ -108,3 +108,65 @@ def test_graph_replays_batch_and_options():
         # eager work between replays
         fhtp.detect_polyline(imgs[0], ks[0], bend=bends[0])
         torch.cuda.synchronize()
+
+
+def test_plan_replays_match_direct_calls(orc):
+    """fhtp_plan_*: one 4096x4096 job and a mixed batch, each recorded once and
+    replayed; images refilled in place between replays; eager work between."""
+    from paper_1912_01884_amd import fhtp
+    dev = require_gpu()
+    big = synth.make_config("4096x4096")
+    img = to_device(big.image, dev)
+    announce("plan 4096x4096: eager")
+    e_s, e_x = [host(t) for t in fhtp.detect_polyline(img, big.k, bend=big.bend)]
+    plan = fhtp.Plan([img], [big.k], bends=[big.bend])
+    (sc, xs), = plan.results
+    for rep in range(3):
+        sc.fill_(-7)
+        xs.fill_(-7)
+        announce(f"plan 4096x4096: replay {rep}")
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(sc), e_s) and np.array_equal(host(xs), e_x), rep
+        fhtp.detect_polyline(img, big.k, bend=big.bend + 1)  # eager work between replays
+        torch.cuda.synchronize()
+    # new contents in the same buffer: the next replay reads them
+    flipped = np.ascontiguousarray(big.image[::-1])
+    img.copy_(torch.from_numpy(flipped).to(dev))
+    f_s, f_x = [host(t) for t in fhtp.detect_polyline(img, big.k, bend=big.bend)]
+    announce("plan 4096x4096: replay on refilled image")
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(sc), f_s) and np.array_equal(host(xs), f_x)
+    plan.destroy()
+
+    batch = synth.make_mixed_batch(32)
+    imgs = [to_device(s.image, dev) for s in batch]
+    ks = [s.k for s in batch]
+    bends = [s.bend for s in batch]
+    announce("plan mixed batch: eager")
+    eager = [(host(a), host(b)) for a, b in fhtp.detect_batch(imgs, ks, bends=bends)]
+    bplan = fhtp.Plan(imgs, ks, bends=bends)
+    for rep in range(3):
+        for a, b in bplan.results:
+            a.fill_(-7)
+            b.fill_(-7)
+        announce(f"plan mixed batch: replay {rep}")
+        bplan.launch()
+        torch.cuda.synchronize()
+        for (a, b), (w_s, w_x) in zip(bplan.results, eager):
+            assert np.array_equal(host(a), w_s) and np.array_equal(host(b), w_x), rep
+        fhtp.detect_polyline(imgs[0], ks[0], bend=bends[0])
+        torch.cuda.synchronize()
+    bplan.destroy()
+
+    # a small plan against the oracle itself
+    small = synth.make_config("64x64")
+    want_s, want_x = orc.detect_polyline(small.image, small.k, bend=small.bend)
+    splan = fhtp.Plan([to_device(small.image, dev)], [small.k], bends=[small.bend])
+    announce("plan 64x64 vs oracle")
+    splan.launch()
+    torch.cuda.synchronize()
+    (a, b), = splan.results
+    assert int(host(a)[0]) == want_s and host(b).tolist() == want_x.tolist()
+    splan.destroy()
