@@ -529,8 +529,11 @@ struct DpPairJob {
     void* a1;            // A_{i+2} plane
     void* a0;            // A_{i+1} plane
     int vin_pitch, h_pitch, v_pitch, a_pitch;
-    int n, w, items_x;
+    int n, w, items_x, items_y;
 };
+
+constexpr int kXcds = 8;         // accelerator dies of the MI355X, each with its own L2
+constexpr int kStripeTiles = 16;  // column tiles per stripe of the pair kernel's item order
 
 // Masks: a thread's loads of V_{i+2} are consecutive rows of one column, so
 // the valid ones form a range of the row index; table loads are not masked
@@ -553,7 +556,22 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
 
     const int n = a.n, w = a.w;
     const int D = 2 * n - 1;
-    const int bx = blockIdx.x % a.items_x, by = blockIdx.x / a.items_x;
+    // Workgroup b runs on XCD b % 8.  Each XCD gets a contiguous run of items
+    // instead, in stripes of kStripeTiles column tiles (every row group of a
+    // stripe before the next stripe), so that the overlapping reads of
+    // neighbouring workgroups (the widened rows, a strip's extra columns, the
+    // diagonal shift between row groups) meet in one L2.
+    int bx, by;
+    {
+        const int total = (int)gridDim.x, b = (int)blockIdx.x;
+        const int xcd = b % kXcds, slot = b / kXcds;
+        const int it = xcd * (total / kXcds) + min(xcd, total % kXcds) + slot;
+        const int per_stripe = kStripeTiles * a.items_y;
+        const int st = it / per_stripe, loc = it - st * per_stripe;
+        const int sw = min(kStripeTiles, a.items_x - st * kStripeTiles);
+        by = loc / sw;
+        bx = st * kStripeTiles + (loc - by * sw);
+    }
     const int X0 = bx * 64;
     const int r0 = by * kPairRows;  // table row of the first displacement of step i
     const int m0 = r0 - B;          // table row of mid[0]
@@ -1272,6 +1290,7 @@ hipError_t run_steps_paired(const DpClass& c, const DpJobSpec& J, hipStream_t s)
             a.n = g.n;
             a.w = g.w;
             a.items_x = items_x;
+            a.items_y = items_y;
             hipError_t e = launch_pair<AT>(J.plan.bound, s, items_x * items_y, a);
             if (e != hipSuccess) return e;
             i -= 2;
