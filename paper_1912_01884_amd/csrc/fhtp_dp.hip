@@ -50,6 +50,7 @@ constexpr int kWaves = 4;      // waves per workgroup, one displacement chunk ea
 constexpr int kMaxFixedB = 16; // largest bend bound with a register-window kernel
 constexpr int kDCGeneric = 16; // displacements per thread in the scanning kernels
 constexpr int kPack = 256;     // images per launch (kernel arguments of up to 32 KB)
+constexpr int kXcds = 8;       // accelerator dies of the MI355X, each with its own L2
 
 // Cache policy of the value and back-pointer plane stores: device scope
 // (SC1), written through the XCD's L2.  The next launch reads the planes from
@@ -71,6 +72,7 @@ struct DpJob {
     int bound;    // mode-0 bound (scanning kernel)
     int full;     // windows cover every displacement
     int items_x;  // workgroups along x
+    int items_y;  // workgroups along the displacements
     int item0;    // first workgroup of this image in the launch
     int vin_pin;  // pin on the cells read from vin: 0 none, 1 x' == pin, 2 x' + d' == pin
     int vin_pin_x;
@@ -106,6 +108,14 @@ struct WalkPack {
     WalkJob job[CAP];
     int count;
 };
+
+// Work item of workgroup b of a grid of `total`: workgroup b runs on XCD
+// b % 8, and each XCD is given a contiguous run of the items, so that
+// neighbouring workgroups share an L2.
+__device__ __forceinline__ int xcd_run_item(int b, int total) {
+    const int xcd = b % kXcds, slot = b / kXcds;
+    return xcd * (total / kXcds) + min(xcd, total % kXcds) + slot;
+}
 
 template <int CAP>
 __device__ __forceinline__ int dp_find_job(const DpPack<CAP>& pk, int item) {
@@ -490,10 +500,14 @@ __device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx,
 // Step with the mode-0 window fixed at compile time.
 template <int B, int DC, typename AT, int CAP>
 __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
-    const int j = dp_find_job(pk, blockIdx.x);
+    // items of an image run down the displacement groups of one column tile
+    // before the next tile, so the window rows shared by vertical neighbours
+    // meet in one L2
+    const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);
+    const int j = dp_find_job(pk, it);
     const DpJob& a = pk.job[j];
-    const int local = blockIdx.x - a.item0;
-    const int bx = local % a.items_x, by = local / a.items_x;
+    const int local = it - a.item0;
+    const int bx = local / a.items_y, by = local - bx * a.items_y;
     const unsigned long long best = fixed_item<B, DC, AT>(a, bx, by);
     finish(a, best, local);
 }
@@ -532,7 +546,6 @@ struct DpPairJob {
     int n, w, items_x, items_y;
 };
 
-constexpr int kXcds = 8;         // accelerator dies of the MI355X, each with its own L2
 constexpr int kStripeTiles = 16;  // column tiles per stripe of the pair kernel's item order
 
 // Masks: a thread's loads of V_{i+2} are consecutive rows of one column, so
@@ -563,9 +576,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
     // diagonal shift between row groups) meet in one L2.
     int bx, by;
     {
-        const int total = (int)gridDim.x, b = (int)blockIdx.x;
-        const int xcd = b % kXcds, slot = b / kXcds;
-        const int it = xcd * (total / kXcds) + min(xcd, total % kXcds) + slot;
+        const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);
         const int per_stripe = kStripeTiles * a.items_y;
         const int st = it / per_stripe, loc = it - st * per_stripe;
         const int sw = min(kStripeTiles, a.items_x - st * kStripeTiles);
@@ -717,10 +728,11 @@ template <typename AT, int CAP>
 __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     __shared__ int res_v[kWaves][kDCGeneric][64];
     __shared__ int res_i[kWaves][kDCGeneric][64];
-    const int jj = dp_find_job(pk, blockIdx.x);
+    const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);  // as dp_step_fixed
+    const int jj = dp_find_job(pk, it);
     const DpJob& a = pk.job[jj];
-    const int local = blockIdx.x - a.item0;
-    const int bx = local % a.items_x, by = local / a.items_x;
+    const int local = it - a.item0;
+    const int bx = local / a.items_y, by = local - bx * a.items_y;
     const int n = a.n, w = a.w;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1200,8 +1212,9 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
             a.key = last ? J->buf.key : nullptr;
             if (st == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);
             a.out_pin_x = J->pin.j == i ? J->pin.x : -1;
+            a.items_y = items_y_of(g, c.dc);
             a.item0 = (int)total;
-            total += (long long)a.items_x * items_y_of(g, c.dc);
+            total += (long long)a.items_x * a.items_y;
             if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
             pk.job[cnt++] = a;
         }
@@ -1267,10 +1280,11 @@ hipError_t run_steps_paired(const DpClass& c, const DpJobSpec& J, hipStream_t s)
             a.htab = J.tables + (size_t)i * band;
             a.vout = vout;
             a.aout = A + (size_t)(i - 1) * plane;
+            a.items_y = items_y_of(g, c.dc);
             a.item0 = 0;
             pk.job[0] = a;
             pk.count = 1;
-            pk.total = items_x * items_y_of(g, c.dc);
+            pk.total = items_x * a.items_y;
             hipError_t e = launch_step<AT, 1>(c, s, pk);
             if (e != hipSuccess) return e;
             i -= 1;
@@ -1305,10 +1319,11 @@ hipError_t run_steps_paired(const DpClass& c, const DpJobSpec& J, hipStream_t s)
     a.vin_pitch = g.pitch;
     a.htab = J.tables;
     a.key = J.buf.key;
+    a.items_y = items_y_of(g, c.dc);
     a.item0 = 0;
     pk.job[0] = a;
     pk.count = 1;
-    pk.total = items_x * items_y_of(g, c.dc);
+    pk.total = items_x * a.items_y;
     return launch_step<AT, 1>(c, s, pk);
 }
 
@@ -1366,8 +1381,9 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
             a.htab = J.tables;
             a.key = J.buf.key;
             first_step_pin(J, a.vin_pin, a.vin_pin_x);
+            a.items_y = items_y_of(J.g, kDCGeneric);
             a.item0 = (int)total;
-            total += (long long)a.items_x * items_y_of(J.g, kDCGeneric);
+            total += (long long)a.items_x * a.items_y;
             if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
             pk.job[q] = a;
         }
