@@ -94,7 +94,7 @@ int plan(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
 }
 
 struct DpLayout {
-    size_t v, a, key, win, end;
+    size_t v, a, key, succ, win, end;
 };
 
 DpLayout dp_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, size_t base) {
@@ -102,7 +102,8 @@ DpLayout dp_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, size_t base)
     L.v = base;  // two value planes used in turn
     L.a = align_up(L.v + 2 * fhtp::dp_plane_bytes(g));
     L.key = align_up(L.a + fhtp::dp_backptr_bytes(g, pl.a16));
-    L.win = align_up(L.key + fhtp::dp_key_count(g) * sizeof(unsigned long long));
+    L.succ = align_up(L.key + fhtp::dp_key_count(g) * sizeof(unsigned long long));
+    L.win = align_up(L.succ + fhtp::dp_key_count(g) * sizeof(int32_t));
     L.end = align_up(L.win + 2 * (size_t)g.D * sizeof(int32_t));
     return L;
 }
@@ -125,6 +126,7 @@ fhtp::DpBuffers dp_buffers(char* ws, const DpLayout& L) {
     b.vplanes = reinterpret_cast<int32_t*>(ws + L.v);
     b.a = ws + L.a;
     b.key = reinterpret_cast<unsigned long long*>(ws + L.key);
+    b.succ = reinterpret_cast<int32_t*>(ws + L.succ);
     b.win = reinterpret_cast<int32_t*>(ws + L.win);
     return b;
 }

@@ -23,9 +23,11 @@
 // The last step (i = 0) writes neither V_0 nor A_1: each workgroup reduces its
 // cells to a packed key ((V + 1) << 32 | ~(x*D + r)) whose maximum is the best
 // score with the smallest (x, d) on ties.  One wave per image then reduces the
-// keys and walks the back-pointers (eq. (5)): the first successor is re-derived
-// from V_1, and later ones are read two bands per memory round trip by loading
-// every candidate of the next band speculatively.
+// keys and walks the back-pointers (eq. (5)): the first successor comes with
+// the best key (the last step records, with each workgroup's key, the argmax
+// of that cell's window of V_1, so A_1 is never stored), and later ones are
+// read several bands per memory round trip by loading every candidate of the
+// next bands speculatively.
 //
 // A query through a point (Sections 2.2-2.3) pins vertex x_j to one column:
 // the step that makes V_j marks every cell of another column infeasible, and
@@ -66,6 +68,7 @@ struct DpJob {
     int32_t* vout;            // V_i (null on the image's last step)
     void* aout;               // A_{i+1} plane (null on the last step)
     unsigned long long* key;  // last step: one packed key per workgroup, else null
+    int32_t* succ;            // last step: per key, the row of that cell's best successor
     const int32_t* win;       // mode-1 windows lo[D], hi[D], or null
     int vin_pitch, h_pitch, v_pitch, a_pitch;
     int n, w;
@@ -91,16 +94,15 @@ struct DpPack {
 // One image in the walk launch.
 struct WalkJob {
     const unsigned long long* key;  // keys of the last step (or of the k = 1 argmax)
-    const int32_t* vin;             // V_1 (the table H_1 when k = 2)
-    const void* a_base;             // plane j holds A_{j+2}, j = 0 .. k-3 (A_1 comes from V_1)
+    const int32_t* succ;            // with each key, the row of that cell's successor (A_1)
+    const void* a_base;             // plane j holds A_{j+2}, j = 0 .. k-3
     size_t a_plane;
     const int32_t* win;
     int32_t* score;
     int32_t* xs;
-    int n_keys, vin_pitch, a_pitch;
+    int n_keys, a_pitch;
     int n, w, k;
     int bound, full;
-    int vin_pin, vin_pin_x;  // as DpJob, for the cells read from vin
 };
 
 template <int CAP>
@@ -207,20 +209,54 @@ __device__ __forceinline__ int load_h(const DpJob& a, int xp, int d) {
     return ok ? v : 0;
 }
 
-// Common end of a step workgroup: on the image's last step its best key goes
-// to slot `slot` (its workgroup index within the image).
-__device__ __forceinline__ void finish(const DpJob& a, unsigned long long best, int slot) {
+// The best cell of a thread on the last step: its packed key and the row
+// d'+n-1 of its best successor (the back-pointer A_1 the step does not store).
+struct Best {
+    unsigned long long key = 0;
+    int succ = 0;
+};
+
+__device__ __forceinline__ void take_best(Best& b, unsigned long long kk, int succ_row) {
+    const bool t = kk > b.key;
+    b.key = t ? kk : b.key;
+    b.succ = t ? (succ_row < 0 ? 0 : succ_row) : b.succ;
+}
+
+// Wave-wide best: the largest key (keys of distinct cells differ) and the
+// successor held by the lane that has it.
+__device__ __forceinline__ Best wave_best(Best b) {
+    const unsigned long long m = wave_max_u64(b.key);
+    const unsigned long long hit = __builtin_amdgcn_ballot_w64(b.key == m);
+    Best r;
+    r.key = m;
+    r.succ = __builtin_amdgcn_readlane(b.succ, (int)__builtin_ctzll(hit));
+    return r;
+}
+
+// Common end of a step workgroup: on the image's last step its best key and
+// that cell's successor go to slot `slot` (its workgroup index within the image).
+__device__ __forceinline__ void finish(const DpJob& a, Best best, int slot) {
     if (!a.key) return;
     __shared__ unsigned long long part[kWaves];
+    __shared__ int part_s[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    best = wave_max_u64(best);
-    if (lane == 0) part[wave] = best;
+    best = wave_best(best);
+    if (lane == 0) {
+        part[wave] = best.key;
+        part_s[wave] = best.succ;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = part[0];
+        int ms = part_s[0];
 #pragma unroll
-        for (int q = 1; q < kWaves; ++q) m = part[q] > m ? part[q] : m;
+        for (int q = 1; q < kWaves; ++q) {
+            const bool t = part[q] > m;
+            m = t ? part[q] : m;
+            ms = t ? part_s[q] : ms;
+        }
         a.key[slot] = m;
+        a.succ[slot] = ms;
     }
 }
 
@@ -260,7 +296,7 @@ constexpr unsigned int kOut = 0x80000000u;  // lane offset past every view: load
 // A_{i+1} (av).
 template <typename AT>
 __device__ __forceinline__ void emit(const DpJob& a, const RowView& ov, const RowView& av, int m,
-                                     int ra, int hval, int xp, int d, unsigned long long& best) {
+                                     int ra, int hval, int xp, int d, Best& best) {
     const int n = a.n, w = a.w;
     const int D = 2 * n - 1;
     const int r = d + n - 1;
@@ -280,8 +316,7 @@ __device__ __forceinline__ void emit(const DpJob& a, const RowView& ov, const Ro
     if (x < 0 || x >= w) return;
     const int val = (m >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hval + m : -1;
     if (last) {
-        const unsigned long long kk = pack_key(val, x, r, D);
-        best = kk > best ? kk : best;
+        take_best(best, pack_key(val, x, r, D), ra);
     } else {
         __builtin_amdgcn_raw_buffer_store_b32(val, ov.rs, x * 4, (int)row_off(ov, r, a.v_pitch, 4),
                                               kStoreScope);
@@ -340,8 +375,7 @@ __device__ __forceinline__ bool wave_is_interior(const DpJob& a, int X0, int r0,
 }
 
 template <int B, int DC, typename AT>
-__device__ __forceinline__ unsigned long long fixed_interior(const DpJob& a, int X0, int r0,
-                                                             int d0) {
+__device__ __forceinline__ Best fixed_interior(const DpJob& a, int X0, int r0, int d0) {
     constexpr int NV = DC + 2 * B;
     const int D = 2 * a.n - 1;
     const int xp = X0 + (int)(threadIdx.x & 63);
@@ -367,13 +401,12 @@ __device__ __forceinline__ unsigned long long fixed_interior(const DpJob& a, int
     __builtin_amdgcn_sched_barrier(0);
     int m[DC], ia[DC];
     window_max<B, DC>(v, m, ia);
-    unsigned long long best = 0;
+    Best best;
     if (a.key) {
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
             const int val = m[j] >= 0 ? hv[j] + m[j] : -1;
-            const unsigned long long kk = pack_key(val, xp - d0 - j, r0 + j, D);
-            best = kk > best ? kk : best;
+            take_best(best, pack_key(val, xp - d0 - j, r0 + j, D), r0 - B + ia[j]);
         }
         return best;
     }
@@ -407,8 +440,7 @@ __device__ __forceinline__ unsigned long long fixed_interior(const DpJob& a, int
 // by ranges and every variable offset part sits in the lane offset, which the
 // hardware checks against the view's extent.
 template <int B, int DC, typename AT>
-__device__ __forceinline__ unsigned long long fixed_general(const DpJob& a, int X0, int r0,
-                                                            int d0) {
+__device__ __forceinline__ Best fixed_general(const DpJob& a, int X0, int r0, int d0) {
     constexpr int NV = DC + 2 * B;
     constexpr int esz = (int)sizeof(AT);
     const int n = a.n, w = a.w;
@@ -450,15 +482,14 @@ __device__ __forceinline__ unsigned long long fixed_general(const DpJob& a, int 
     const int jn = col_ok ? min(DC, D - r0) : 0;
     const int xj = xp - d0;  // x of cell j is xj - j
     const bool last = a.key != nullptr;
-    unsigned long long best = 0;
+    Best best;
     if (last) {
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
             const int x = xj - j;
             const bool live = j < jn && (unsigned)x < (unsigned)w;
             const int val = (m[j] >= 0 && (a.out_pin_x < 0 || x == a.out_pin_x)) ? hv[j] + m[j] : -1;
-            const unsigned long long kk = live ? pack_key(val, x, r0 + j, D) : 0ull;
-            best = kk > best ? kk : best;
+            take_best(best, live ? pack_key(val, x, r0 + j, D) : 0ull, rlo + ia[j]);
         }
         return best;
     }
@@ -488,7 +519,7 @@ __device__ __forceinline__ unsigned long long fixed_general(const DpJob& a, int 
 }
 
 template <int B, int DC, typename AT>
-__device__ __forceinline__ unsigned long long fixed_item(const DpJob& a, int bx, int by) {
+__device__ __forceinline__ Best fixed_item(const DpJob& a, int bx, int by) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int X0 = bx * 64;
     const int r0 = (by * kWaves + wave) * DC;  // table row of this wave's first displacement
@@ -508,7 +539,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
     const DpJob& a = pk.job[j];
     const int local = it - a.item0;
     const int bx = local / a.items_y, by = local - bx * a.items_y;
-    const unsigned long long best = fixed_item<B, DC, AT>(a, bx, by);
+    const Best best = fixed_item<B, DC, AT>(a, bx, by);
     finish(a, best, local);
 }
 
@@ -789,7 +820,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
             m = take ? col_v[q][lane] : m;
             ia = take ? col_i[q][lane] : ia;
         }
-        unsigned long long best = 0;
+        Best best;
 #pragma unroll
         for (int j = 0; j < kDCGeneric; ++j) {
             if (j >= jn) break;
@@ -858,7 +889,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
         }
         ja = jb + 1;
     }
-    unsigned long long best = 0;
+    Best best;
 #pragma unroll
     for (int j = 0; j < kDCGeneric; ++j) {
         if (j >= jn) break;
@@ -882,15 +913,14 @@ __global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
     const int chunk = by * kWaves + wave;
     const int D = 2 * n - 1;
     const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
-    unsigned long long best = 0;
+    Best best;  // k = 1: no successor
     for (int j = 0; j < kDCGeneric; ++j) {
         const int r = chunk * kDCGeneric + j;
         const int d = r - (n - 1);
         if (r >= D || (unsigned)(x - mk.xlo) >= (unsigned)mk.xlen ||
             (unsigned)(x + d - mk.tlo) >= (unsigned)mk.tlen)
             continue;
-        const unsigned long long kk = pack_key(a.htab[(size_t)r * a.h_pitch + x], x, r, D);
-        best = kk > best ? kk : best;
+        take_best(best, pack_key(a.htab[(size_t)r * a.h_pitch + x], x, r, D), 0);
     }
     finish(a, best, local);
 }
@@ -963,18 +993,26 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
     const int lane = threadIdx.x;
     const int n = a.n, w = a.w, k = a.k;
     const int D = 2 * n - 1;
-    unsigned long long kv = 0;
+    // The keys of the last step and, with each, the successor of that cell.
+    Best bk;
     for (int q0 = 0; q0 < a.n_keys; q0 += 64 * 8) {
         unsigned long long t[8];
+        int sc[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int q = q0 + u * 64 + lane;
             t[u] = a.key[q < a.n_keys ? q : 0];
+            sc[u] = a.succ[q < a.n_keys ? q : 0];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) kv = t[u] > kv ? t[u] : kv;
+        for (int u = 0; u < 8; ++u) {
+            const bool tk = t[u] > bk.key;
+            bk.key = tk ? t[u] : bk.key;
+            bk.succ = tk ? sc[u] : bk.succ;
+        }
     }
-    kv = wave_max_u64(kv);
+    bk = wave_best(bk);
+    const unsigned long long kv = bk.key;
     const unsigned int lin = 0xffffffffu - (unsigned int)(kv & 0xffffffffull);
     const unsigned int xu = lin / (unsigned int)D;
     int x = (int)xu;
@@ -985,27 +1023,14 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
     }
     if (lane == 0) a.xs[0] = x;
     if (k >= 2) {
-        // First successor from V_1: the smallest d' of the window reaching its maximum.
+        // First successor: recorded by the last step with the cell's key (the
+        // smallest d' of its window reaching the maximum of V_1).
         const int x1 = x + r - (n - 1);
         if (x1 < 0 || x1 >= w) {
             if (lane == 0) *a.score = -1;
             return;
         }
-        int lo, hi;
-        window_of(n, a.full, a.win, a.bound, r - (n - 1), lo, hi);
-        const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
-        unsigned long long bestk = 0;
-        for (int base = lo; base <= hi; base += 64) {
-            const int dp = base + lane;
-            const int v = load_v(a.vin, a.vin_pitch, x1, dp, n, mk);
-            const unsigned long long kk =
-                dp <= hi ? ((unsigned long long)(unsigned int)(v + 2) << 32) |
-                               (unsigned long long)(0xffffffffu - (unsigned int)(dp + n - 1))
-                         : 0ull;
-            const unsigned long long m = wave_max_u64(kk);
-            bestk = m > bestk ? m : bestk;
-        }
-        const int r1 = (int)(0xffffffffu - (unsigned int)(bestk & 0xffffffffull));
+        const int r1 = bk.succ;
         if (lane == 0) a.xs[1] = x1;
         x = x1;
         r = r1;
@@ -1210,6 +1235,7 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
             a.vout = last ? nullptr : J->buf.vplanes + (size_t)(i & 1) * plane;
             a.aout = last ? nullptr : static_cast<AT*>(J->buf.a) + (size_t)(i - 1) * plane;
             a.key = last ? J->buf.key : nullptr;
+            a.succ = last ? J->buf.succ : nullptr;
             if (st == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);
             a.out_pin_x = J->pin.j == i ? J->pin.x : -1;
             a.items_y = items_y_of(g, c.dc);
@@ -1319,6 +1345,7 @@ hipError_t run_steps_paired(const DpClass& c, const DpJobSpec& J, hipStream_t s)
     a.vin_pitch = g.pitch;
     a.htab = J.tables;
     a.key = J.buf.key;
+    a.succ = J.buf.succ;
     a.items_y = items_y_of(g, c.dc);
     a.item0 = 0;
     pk.job[0] = a;
@@ -1338,10 +1365,9 @@ hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
             const DpClass c = class_of(J);
             WalkJob& a = pk.job[q];
             a.key = J.buf.key;
+            a.succ = J.buf.succ;
             a.n_keys = g.k == 1 ? (int)(((g.w + 63) / 64) * items_y_of(g, kDCGeneric))
                                 : (int)(((g.w + 63) / 64) * items_y_of(g, c.dc));
-            a.vin = g.k == 2 ? J.tables + (size_t)g.D * g.W : J.buf.vplanes + (size_t)g.D * g.pitch;
-            a.vin_pitch = g.k == 2 ? g.W : g.pitch;
             a.a_base = J.buf.a;
             a.a_plane = (size_t)g.D * g.pitch;
             a.a_pitch = g.pitch;
@@ -1353,9 +1379,6 @@ hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
             a.win = J.plan.kind == WindowKind::Angle ? J.buf.win : nullptr;
             a.score = J.score;
             a.xs = J.xs;
-            a.vin_pin = 0;
-            a.vin_pin_x = 0;
-            if (g.k == 2) first_step_pin(J, a.vin_pin, a.vin_pin_x);
         }
         pk.count = cnt;
         hipLaunchKernelGGL((walk<AT, CAP>), dim3(cnt), dim3(64), 0, s, pk);
@@ -1380,6 +1403,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
             DpJob a = base_job(J);
             a.htab = J.tables;
             a.key = J.buf.key;
+            a.succ = J.buf.succ;
             first_step_pin(J, a.vin_pin, a.vin_pin_x);
             a.items_y = items_y_of(J.g, kDCGeneric);
             a.item0 = (int)total;

@@ -55,6 +55,7 @@ struct DpBuffers {
     int32_t* vplanes;         // two value planes [2][D][pitch], used in turn
     void* a;                  // back-pointer planes [k-2][D][pitch]
     unsigned long long* key;  // packed argmax keys, one per workgroup of the last step
+    int32_t* succ;            // per key: the row d'+n-1 of that cell's best successor
     int32_t* win;             // angle windows lo[D], hi[D]
 };
 
