@@ -575,6 +575,14 @@ struct DpPairJob {
     void* a0;            // A_{i+1} plane
     int vin_pitch, h_pitch, v_pitch, a_pitch;
     int n, w, items_x, items_y;
+    int item0;  // first workgroup of this image in the launch
+};
+
+// CAP images per launch, as DpPack.
+template <int CAP>
+struct DpPairPack {
+    DpPairJob job[CAP];
+    int count;
 };
 
 constexpr int kStripeTiles = 16;  // column tiles per stripe of the pair kernel's item order
@@ -586,8 +594,8 @@ constexpr int kStripeTiles = 16;  // column tiles per stripe of the pair kernel'
 // row index and write nothing outside their rows.  All variable parts of an
 // offset go to the lane offset, which is what the hardware checks against
 // the view's extent.
-template <int B, typename AT>
-__global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
+template <int B, typename AT, int CAP>
+__global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP> pk) {
     constexpr int RM = kPairRows + 2 * B;  // rows of V_{i+1} the workgroup needs
     constexpr int NS = (RM + kStrip - 1) / kStrip;
     constexpr int SC = 64 + kStrip - 1;    // successor columns of one strip
@@ -598,18 +606,31 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairJob a) {
     constexpr int LWP = 64 + 2 * LP;       // strip cells outside the tile land in the padding
     __shared__ int mid[NS * kStrip][LWP];  // V_{i+1}(X0 + c, row m0 + q) at [q][LP + c]
 
+    // Workgroup b runs on XCD b % 8.  Each XCD gets a contiguous run of items
+    // instead, an image's items in stripes of kStripeTiles column tiles (every
+    // row group of a stripe before the next stripe), so that the overlapping
+    // reads of neighbouring workgroups (the widened rows, a strip's extra
+    // columns, the diagonal shift between row groups) meet in one L2.
+    const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);
+    int jj = 0;  // the last image whose first item is <= it (item0 ascends)
+    if constexpr (CAP > 1) {
+        int hi = pk.count - 1;
+        while (jj < hi) {
+            const int md = (jj + hi + 1) >> 1;
+            if (pk.job[md].item0 <= it)
+                jj = md;
+            else
+                hi = md - 1;
+        }
+    }
+    const DpPairJob& a = pk.job[jj];
     const int n = a.n, w = a.w;
     const int D = 2 * n - 1;
-    // Workgroup b runs on XCD b % 8.  Each XCD gets a contiguous run of items
-    // instead, in stripes of kStripeTiles column tiles (every row group of a
-    // stripe before the next stripe), so that the overlapping reads of
-    // neighbouring workgroups (the widened rows, a strip's extra columns, the
-    // diagonal shift between row groups) meet in one L2.
     int bx, by;
     {
-        const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);
+        const int local = CAP > 1 ? it - a.item0 : it;  // one image: item0 is 0
         const int per_stripe = kStripeTiles * a.items_y;
-        const int st = it / per_stripe, loc = it - st * per_stripe;
+        const int st = local / per_stripe, loc = local - st * per_stripe;
         const int sw = min(kStripeTiles, a.items_x - st * kStripeTiles);
         by = loc / sw;
         bx = st * kStripeTiles + (loc - by * sw);
@@ -1252,11 +1273,12 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
     return hipSuccess;
 }
 
-template <typename AT>
-hipError_t launch_pair(int bound, hipStream_t s, int grid, const DpPairJob& a) {
-#define FHTP_B(BB)                                                                              \
-    case BB:                                                                                    \
-        hipLaunchKernelGGL((dp_pair_fixed<BB, AT>), dim3(grid), dim3(64 * kPairWaves), 0, s, a); \
+template <typename AT, int CAP>
+hipError_t launch_pair(int bound, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
+#define FHTP_B(BB)                                                                          \
+    case BB:                                                                                \
+        hipLaunchKernelGGL((dp_pair_fixed<BB, AT, CAP>), dim3(grid), dim3(64 * kPairWaves), 0, \
+                           s, pk);                                                          \
         return hipSuccess;
     switch (bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
@@ -1266,62 +1288,92 @@ hipError_t launch_pair(int bound, hipStream_t s, int grid, const DpPairJob& a) {
 #undef FHTP_B
 }
 
-// Two steps per launch suit a single image whose step grid leaves the chip
-// latency-bound (the 8-displacement chunk), with the fixed window, no pin and
-// at least one pair of steps before the last; the byte offsets inside a
-// workgroup's rows must fit 32 bits.
+// Two steps per launch need the fixed window, the 8-displacement chunk (an
+// image whose step grid leaves the chip latency-bound on its own), no pin,
+// and byte offsets inside a workgroup's rows that fit 32 bits.
 bool pairs_apply(const DpJobSpec& J) {
     const Geometry& g = J.g;
     const long long rows = kPairRows + 4LL * kMaxFixedB + kStrip;  // the widest view
     const long long pitch = std::max(g.W, g.pitch);
-    return J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC && J.pin.j < 0 && g.k >= 4 &&
+    return J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC && J.pin.j < 0 && g.k >= 2 &&
            rows * pitch * 4 < 0x7fffffffLL;
 }
 
-// Steps of one image with bands k-2 .. 1 taken two per launch (one single
-// step first when their count is odd), then the last step.  The launches
-// that make V alternate between the two value planes so that V_1 lands in
-// plane 1, where the last step and the walk read it; a launch never writes
-// the plane it reads.
-template <typename AT>
-hipError_t run_steps_paired(const DpClass& c, const DpJobSpec& J, hipStream_t s) {
-    const Geometry& g = J.g;
-    const size_t band = (size_t)g.D * g.W;
-    const size_t plane = (size_t)g.D * g.pitch;
-    const int P = g.k - 2;                   // bands k-2 .. 1 before the last step
-    const int launches = (P & 1) + P / 2;   // launches that make V
-    const int items_x = (g.w + 63) / 64;
-    const int items_y = (g.D + kPairRows - 1) / kPairRows;
-    const int32_t* vin = J.tables + (size_t)(g.k - 1) * band;
-    int vin_pitch = g.W;
-    int i = g.k - 2;  // next band to make
-    for (int L = 0; L < launches; ++L) {
-        int32_t* vout = J.buf.vplanes + (size_t)(((launches - 1 - L) & 1) ? 0 : 1) * plane;
-        AT* A = static_cast<AT*>(J.buf.a);
-        if (L == 0 && (P & 1)) {
-            DpPack<1> pk{};
-            DpJob a = base_job(J);
-            a.vin = vin;
-            a.vin_pitch = vin_pitch;
-            a.htab = J.tables + (size_t)i * band;
-            a.vout = vout;
-            a.aout = A + (size_t)(i - 1) * plane;
-            a.items_y = items_y_of(g, c.dc);
-            a.item0 = 0;
-            pk.job[0] = a;
-            pk.count = 1;
-            pk.total = items_x * a.items_y;
-            hipError_t e = launch_step<AT, 1>(c, s, pk);
-            if (e != hipSuccess) return e;
-            i -= 1;
+// Steps of a pack of images of one class with bands k-2 .. 1 taken two per
+// launch, then the last step.  Images are aligned at the end: every image's
+// last step is in the final launch and its pairs in the launches just before
+// it; an image with an odd count of bands before the last step does its top
+// band alone in one launch ahead of all pairs.  Per image, the launches that
+// make V alternate between its two value planes so that V_1 lands in plane 1,
+// where the last step reads it; a launch never writes the plane it reads, and
+// an image that sits out a launch leaves its planes untouched.
+template <typename AT, int CAP>
+hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*>& jobs,
+                            hipStream_t s) {
+    int Q = 0;  // pair launches
+    bool singles = false;
+    for (const DpJobSpec* J : jobs) {
+        Q = std::max(Q, (J->g.k - 2) / 2);
+        singles = singles || ((J->g.k - 2) & 1);
+    }
+    // Input plane of V-launch j of an image (j = 0: the table H_{k-1}) and its
+    // output plane.
+    auto plane_of = [](const DpJobSpec& J, int j) {
+        const int P = J.g.k - 2;
+        const int m = (P & 1) + P / 2;  // V-launches of the image
+        return J.buf.vplanes + (size_t)(((m - 1 - j) & 1) ? 0 : 1) * ((size_t)J.g.D * J.g.pitch);
+    };
+    auto input_of = [&](const DpJobSpec& J, int j, const int32_t*& vin, int& pitch) {
+        if (j == 0) {
+            vin = J.tables + (size_t)(J.g.k - 1) * ((size_t)J.g.D * J.g.W);
+            pitch = J.g.W;
         } else {
-            // bands i (phase 1) and i-1 (phase 2)
+            vin = plane_of(J, j - 1);
+            pitch = J.g.pitch;
+        }
+    };
+    if (singles) {
+        DpPack<CAP> pk{};
+        long long total = 0;
+        int cnt = 0;
+        for (const DpJobSpec* J : jobs) {
+            const Geometry& g = J->g;
+            if (!((g.k - 2) & 1)) continue;
+            const int i = g.k - 2;  // its top band
+            DpJob a = base_job(*J);
+            input_of(*J, 0, a.vin, a.vin_pitch);
+            a.htab = J->tables + (size_t)i * ((size_t)g.D * g.W);
+            a.vout = plane_of(*J, 0);
+            a.aout = static_cast<AT*>(J->buf.a) + (size_t)(i - 1) * ((size_t)g.D * g.pitch);
+            a.items_y = items_y_of(g, c.dc);
+            a.item0 = (int)total;
+            total += (long long)a.items_x * a.items_y;
+            if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            pk.job[cnt++] = a;
+        }
+        pk.count = cnt;
+        pk.total = (int)total;
+        hipError_t e = launch_step<AT, CAP>(c, s, pk);
+        if (e != hipSuccess) return e;
+    }
+    for (int L = 0; L < Q; ++L) {
+        DpPairPack<CAP> pk{};
+        long long total = 0;
+        int cnt = 0;
+        for (const DpJobSpec* J : jobs) {
+            const Geometry& g = J->g;
+            const int P = g.k - 2, np = P / 2, odd = P & 1;
+            const int t = L - (Q - np);  // the image's pair index in this launch
+            if (t < 0) continue;
+            const int i = P - odd - 2 * t;  // phase-1 band; phase 2 makes band i-1
+            const size_t band = (size_t)g.D * g.W;
+            const size_t plane = (size_t)g.D * g.pitch;
+            AT* A = static_cast<AT*>(J->buf.a);
             DpPairJob a{};
-            a.vin = vin;
-            a.vin_pitch = vin_pitch;
-            a.h1 = J.tables + (size_t)i * band;
-            a.h0 = J.tables + (size_t)(i - 1) * band;
-            a.vout = vout;
+            input_of(*J, odd + t, a.vin, a.vin_pitch);
+            a.h1 = J->tables + (size_t)i * band;
+            a.h0 = J->tables + (size_t)(i - 1) * band;
+            a.vout = plane_of(*J, odd + t);
             a.a1 = A + (size_t)(i - 1) * plane;  // A_{i+1}
             a.a0 = A + (size_t)(i - 2) * plane;  // A_i
             a.h_pitch = g.W;
@@ -1329,29 +1381,39 @@ hipError_t run_steps_paired(const DpClass& c, const DpJobSpec& J, hipStream_t s)
             a.a_pitch = g.pitch;
             a.n = g.n;
             a.w = g.w;
-            a.items_x = items_x;
-            a.items_y = items_y;
-            hipError_t e = launch_pair<AT>(J.plan.bound, s, items_x * items_y, a);
-            if (e != hipSuccess) return e;
-            i -= 2;
+            a.items_x = (g.w + 63) / 64;
+            a.items_y = (g.D + kPairRows - 1) / kPairRows;
+            a.item0 = (int)total;
+            total += (long long)a.items_x * a.items_y;
+            if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            pk.job[cnt++] = a;
         }
-        vin = vout;
-        vin_pitch = g.pitch;
+        pk.count = cnt;
+        hipError_t e = launch_pair<AT, CAP>(jobs[0]->plan.bound, s, (int)total, pk);
+        if (e != hipSuccess) return e;
     }
-    // last step: V_1 (plane 1) to the keys
-    DpPack<1> pk{};
-    DpJob a = base_job(J);
-    a.vin = J.buf.vplanes + plane;
-    a.vin_pitch = g.pitch;
-    a.htab = J.tables;
-    a.key = J.buf.key;
-    a.succ = J.buf.succ;
-    a.items_y = items_y_of(g, c.dc);
-    a.item0 = 0;
-    pk.job[0] = a;
-    pk.count = 1;
-    pk.total = items_x * a.items_y;
-    return launch_step<AT, 1>(c, s, pk);
+    // last step of every image: V_1 (or the table H_1 when k = 2) to the keys
+    DpPack<CAP> pk{};
+    long long total = 0;
+    int cnt = 0;
+    for (const DpJobSpec* J : jobs) {
+        const Geometry& g = J->g;
+        const int P = g.k - 2;
+        const int m = (P & 1) + P / 2;
+        DpJob a = base_job(*J);
+        input_of(*J, m, a.vin, a.vin_pitch);
+        a.htab = J->tables;
+        a.key = J->buf.key;
+        a.succ = J->buf.succ;
+        a.items_y = items_y_of(g, c.dc);
+        a.item0 = (int)total;
+        total += (long long)a.items_x * a.items_y;
+        if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        pk.job[cnt++] = a;
+    }
+    pk.count = cnt;
+    pk.total = (int)total;
+    return launch_step<AT, CAP>(c, s, pk);
 }
 
 template <typename AT, int CAP>
@@ -1432,8 +1494,14 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
         for (size_t q0 = 0; q0 < group.size(); q0 += CAP) {
             std::vector<const DpJobSpec*> pack(group.begin() + q0,
                                                group.begin() + std::min(group.size(), q0 + CAP));
-            hipError_t e = CAP == 1 && pairs_apply(*pack[0]) ? run_steps_paired<AT>(c, *pack[0], s)
-                                                             : run_steps<AT, CAP>(c, pack, s);
+            bool paired = false;  // every image qualifies and one has a pair of steps
+            bool all = true;
+            for (const DpJobSpec* J : pack) {
+                all = all && pairs_apply(*J);
+                paired = paired || J->g.k >= 4;
+            }
+            hipError_t e = all && paired ? run_steps_paired<AT, CAP>(c, pack, s)
+                                         : run_steps<AT, CAP>(c, pack, s);
             if (e != hipSuccess) return e;
         }
     }
