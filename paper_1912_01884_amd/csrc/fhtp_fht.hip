@@ -407,19 +407,28 @@ __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
     const int32_t* base = J.sub + (size_t)band * M * 2 * (1 << kRegMaxP) * row;
     int32_t* out = J.tables + (size_t)band * D * row;
     const int xo = dir == 0 ? c : (W - 1 - c);
+    // Every load of the workgroup's shifts first (all in flight together),
+    // then the sums and the stores.
+    int32_t acc[kShiftGroup];
+#pragma unroll
     for (int t = 0; t < kShiftGroup; ++t) {
         const int s = g * kShiftGroup + t;
-        if (dir == 1 && s == 0) continue;
         const int sf = s >> SH;
-        int32_t acc = 0;
+        int32_t a = 0;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             int cc = c + sub_block_offset<SH>(s, m);
             cc -= cc >= W ? W : 0;  // offsets are below n < W, so one wrap at most
-            acc += base[((size_t)(m * 2 + dir) * (1 << kRegMaxP) + sf) * row + cc];
+            a += base[((size_t)(m * 2 + dir) * (1 << kRegMaxP) + sf) * row + cc];
         }
+        acc[t] = a;
+    }
+#pragma unroll
+    for (int t = 0; t < kShiftGroup; ++t) {
+        const int s = g * kShiftGroup + t;
+        if (dir == 1 && s == 0) continue;
         const int r = dir == 0 ? (n - 1 + s) : (n - 1 - s);
-        out[(size_t)r * row + xo] = acc;
+        out[(size_t)r * row + xo] = acc[t];
     }
 }
 
