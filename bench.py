@@ -30,8 +30,8 @@ HBM_PEAK_GBPS = 8000.0
 # then WRITE_SIZE), each scaled by what the same counter reads for a copy of a
 # known size in the same run.  Valid only for the kernel source they were
 # taken on (sha256 of csrc/fhtp_fht.hip); otherwise the traffic is unknown.
-FHT_TRAFFIC = {"source_sha256": "b58ad63c9c5f8b9312003c86060e83637f6b1908ce53c21aeb40e01c67fcc797",
-               "fetch_bytes": 36224478, "write_bytes": 140754944}
+FHT_TRAFFIC = {"source_sha256": "cdac1114378378f7aa191d74cb694334aabca5a632807fc827e676ba11e8b4d3",
+               "fetch_bytes": 36157260, "write_bytes": 140754944}
 
 
 def byte_model(h, w, k, bpp):
