@@ -87,3 +87,26 @@ def test_batch_repeat_identical():
     for q in range(len(batch)):
         assert np.array_equal(host(a[q][0]), host(b[q][0]))
         assert np.array_equal(host(a[q][1]), host(b[q][1]))
+
+
+def test_paired_batch_odd_and_even_band_counts(orc):
+    """One window class whose images have every band count from 2 to 9: the
+    two-step launches align the images at their last step, and the images with
+    an odd count of bands before it take their top band in a launch of its own."""
+    from paper_1912_01884_amd import fhtp
+    dev = require_gpu()
+    rng = _rng(7)
+    jobs = []  # (image, k)
+    for k in (2, 3, 4, 5, 6, 7, 8, 9, 3, 5):
+        n = int(rng.choice([8, 16, 32]))
+        w = int(rng.integers(40, 300))
+        jobs.append((rng.integers(0, 256, size=(n * k, w)).astype(np.uint8), k))
+    imgs = [to_device(img, dev) for img, _ in jobs]
+    ks = [k for _, k in jobs]
+    announce(f"paired batch of {len(jobs)} images, k = {ks}")
+    out = fhtp.detect_batch(imgs, ks, bends=[3] * len(jobs))
+    torch.cuda.synchronize()
+    for q, (img, k) in enumerate(jobs):
+        want_s, want_x = orc.detect_polyline(img, k, bend=3)
+        assert int(host(out[q][0])[0]) == want_s, q
+        assert host(out[q][1]).tolist() == want_x.tolist(), q
