@@ -168,16 +168,30 @@ __device__ __forceinline__ VMask vmask(int w, int pin, int pin_x) {
     return m;
 }
 
-// V_{i+1}(x', d') with the feasibility mask: zero-based row r' = d' + n - 1.
-// The load is unconditional (masked lanes read element 0, which always
-// exists) so that every load of a thread can be in flight at once.
+// The displacements d' whose cells V_{i+1}(x', d') are feasible form one
+// range [dlo, dhi] for a column x' (empty when dhi < dlo): d' in
+// [-(n-1), n-1] with x' + d' in [tlo, tlo + tlen), and x' passing the pin.
+struct DRange {
+    int dlo, dhi;
+};
+
+__device__ __forceinline__ DRange drange(int n, int xp, const VMask& mk) {
+    DRange r;
+    r.dlo = max(-(n - 1), mk.tlo - xp);
+    r.dhi = min(n - 1, mk.tlo + mk.tlen - 1 - xp);
+    if ((unsigned)(xp - mk.xlo) >= (unsigned)mk.xlen) r.dhi = r.dlo - 1;
+    return r;
+}
+
+// V_{i+1}(x', d'), or -1 outside the feasible range.  The load is
+// unconditional (other lanes read element 0, which always exists) and the
+// mask is two compares, no branch, so that every load of a tile is in flight
+// at once.
 __device__ __forceinline__ int load_v(const int32_t* __restrict__ vin, int pitch, int xp, int dp,
-                                      int n, const VMask& mk) {
-    const int r = dp + n - 1;
-    const bool ok = (unsigned)(xp - mk.xlo) < (unsigned)mk.xlen &&
-                    (unsigned)r < (unsigned)(2 * n - 1) &&
-                    (unsigned)(xp + dp - mk.tlo) < (unsigned)mk.tlen;
-    const unsigned int off = ok ? (unsigned int)r * (unsigned int)pitch + (unsigned int)xp : 0u;
+                                      int n, const DRange& dr) {
+    const bool ok = (dp >= dr.dlo) & (dp <= dr.dhi);
+    const unsigned int off =
+        ok ? (unsigned int)(dp + n - 1) * (unsigned int)pitch + (unsigned int)xp : 0u;
     const int v = vin[off];
     return ok ? v : -1;
 }
@@ -793,7 +807,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     const int d0 = -(n - 1) + chunk * kDCGeneric;
     const int D = 2 * n - 1;
     const int jn = min(kDCGeneric, D - (d0 + n - 1));  // displacements of this wave
-    const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
+    const DRange mk = drange(n, xp, vmask(w, a.vin_pin, a.vin_pin_x));
     const bool last = a.key != nullptr;  // no planes to write (views unused)
     const RowView ov = row_view(last ? a.vin : a.vout, a.v_pitch, 4, d0 + n - 1, kDCGeneric, D);
     const RowView av = row_view(last ? a.vin : a.aout, a.a_pitch, sizeof(AT), d0 + n - 1,
