@@ -50,7 +50,7 @@ namespace {
 
 constexpr int kWaves = 4;      // waves per workgroup, one displacement chunk each
 constexpr int kMaxFixedB = 16; // largest bend bound with a register-window kernel
-constexpr int kDCGeneric = 16; // displacements per thread in the scanning kernels
+constexpr int kDCGeneric = 8;  // displacements per thread in the scanning kernels
 constexpr int kPack = 256;     // images per launch (kernel arguments of up to 32 KB)
 constexpr int kXcds = 8;       // accelerator dies of the MI355X, each with its own L2
 
@@ -784,10 +784,10 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
 // group is [lo, c] + [c+1, hi].  One descending scan from c gives every
 // [lo, c] maximum (recorded as the scan passes each lo) and one ascending scan
 // from c+1 gives every [c+1, hi] maximum, so each V cell of the union of the
-// windows is read and compared once, with the loads issued sixteen at a time.
+// windows is read and compared once, with the loads issued eight at a time.
 // Ties keep the smallest d' (descending scans take equal values, ascending
 // ones only larger values, and the [lo, c] part wins ties).
-constexpr int kScanTile = 16;
+constexpr int kScanTile = 8;
 constexpr int kEmpty = -2147483647 - 1;  // no cell yet (below every V, -1 included)
 
 template <typename AT, int CAP>
