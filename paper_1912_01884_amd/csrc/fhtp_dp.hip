@@ -35,10 +35,17 @@
 // applied where the table H_{k-1} is read as V_{k-1}.  Every other bend stays
 // bounded as usual, so the result is the best polyline through the point.
 //
-// Every launch takes a pack of images (jobs).  An image with k bands takes
-// part in the step launches s = 0 .. k-2 of its pack (band i = k-2-s), so a
-// batch of images of different sizes shares one launch per step instead of one
-// per image and step.
+// With the fixed window, two steps share a launch (dp_pair_fixed): a step
+// reads V_{i+1} only in its own successor columns and in its displacement rows
+// widened by the bound, so a workgroup computes exactly those cells of V_{i+1}
+// from V_{i+2} in LDS and goes on to step i, and V_{i+1} never goes through
+// memory.
+//
+// Every launch takes a pack of images (jobs), so a batch of images of
+// different sizes shares one launch per step (or pair of steps) instead of one
+// per image and step.  One step per launch: an image with k bands takes part
+// in the launches s = 0 .. k-2 of its pack (band i = k-2-s).  Two steps per
+// launch: images are aligned at their last step (run_steps_paired).
 #include <algorithm>
 #include <type_traits>
 #include <vector>
