@@ -40,8 +40,8 @@ def byte_model(h, w, k, bpp):
     D, W = 2 * n - 1, w + n
     image = h * w * bpp
     tables = 4 * k * D * W
-    # back-pointer planes for bands 2..k-1 (the first successor is re-derived
-    # from V_1 during the walk)
+    # back-pointer planes for bands 2..k-1 (the first successor is recorded by
+    # the last step with its keys)
     backptr = max(k - 2, 0) * D * w * (1 if D <= 256 else 2)
     return {"image": image, "tables_write": tables, "tables_read": tables, "backptr": backptr,
             "total": image + 2 * tables + backptr, "fht_kernel": image + tables}
