@@ -158,6 +158,8 @@ PAIRED = [
     (128 * 4, 130, 4),   # n = 128: one pair, 255 displacements
     (16 * 9, 70, 9),     # n = 16: odd count
     (8 * 12, 65, 12),    # n = 8: windows wider than the displacement range
+    (256 * 4, 333, 4),   # n = 256: 16-bit back-pointers, one pair
+    (256 * 6, 100, 6),   # n = 256: two pairs
 ]
 
 
