@@ -174,6 +174,22 @@ def test_detect_paired_steps(dev, F, orc, h, w, k, B):
     assert host(xs).tolist() == want_x.tolist()
 
 
+def test_maximum_width(dev, F, orc):
+    """The widest image the library takes (2^20 columns): 16384 column tiles per
+    step launch, tables and planes of several hundred MB."""
+    w = 1 << 20
+    img = _img(32, w, np.uint8, 4242, 7)
+    want_s, want_x = orc.detect_polyline(img, 4, bend=3)
+    announce(f"detect maximum width 32x{w} k=4 B=3")
+    sc, xs = F.detect_polyline(to_device(img, dev), 4, bend=3)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+    tables = host(F.fht_bands(to_device(img, dev), 4))
+    want_t = orc.fht_bands(img, 4)
+    assert np.array_equal(tables[:, :, :4096], want_t[:, :, :4096])
+    assert np.array_equal(tables[:, :, -4096:], want_t[:, :, -4096:])
+
+
 def test_saturated_image(dev, F, orc):
     img = np.full((256, 301), 255, np.uint8)
     announce("detect saturated 256x301")
