@@ -71,8 +71,39 @@ def cpu_baseline(img, k, bend, seconds):
         if el >= seconds:
             break
     return {"value": round(h * w * runs / el / 1e6, 3), "unit": "Mpix/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{runs} full detection(s) of the {h}x{w} image, {el:.1f} s"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def single_detections(step, stream, reps, flush=None):
+    """Per-detection times (ms) of `reps` detections, each timed alone with
+    events; `flush` (outside the timed region) evicts the caches first."""
+    import torch
+    out = []
+    for _ in range(reps):
+        if flush is not None:
+            flush()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        step()
+        b.record(stream)
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    out.sort()
+    return {"median": round(out[len(out) // 2], 4), "min": round(out[0], 4), "reps": reps}
 
 
 def mixed_batch(n_images, reps, dev, stream):
@@ -295,6 +326,14 @@ def main():
     launch = ("fhtp_plan_launch: hip graph replay of one detection" if ms_graph <= ms_eager
               else "fhtp_detect_polyline: one call per detection, kernels launched on the stream")
 
+    # Single detections timed one by one: warm (tables and planes of the
+    # previous detection still in L2/MALL) and cold (a 1 GiB buffer written
+    # between detections, outside the timed region, evicts L2 and MALL).
+    single_warm = single_detections(step, stream, 20)
+    flush_buf = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    single_cold = single_detections(step, stream, 10, flush=lambda: flush_buf.fill_(1))
+    del flush_buf
+
     # Phase timings on the same stream: the band FHT (one kernel) and the DP.
     tables = torch.empty(fhtp.table_shape(h, w, k), dtype=torch.int32, device=dev)
     fws_n = fhtp.fht_workspace_bytes(dt, h, w, k)
@@ -355,6 +394,7 @@ def main():
         "eager_ms_per_step": round(ms_eager, 4),
         "graph_ms_per_step": round(ms_graph, 4),
         "phase_ms": {"fht_bands": round(ms_fht, 4), "polyline_dp": round(ms_dp, 4)},
+        "single_detection_ms": {"warm": single_warm, "cold": single_cold},
         "roofline": {"bound": "hbm", "kernel": "fht_reg_kernel",
                      "achieved": round(fht_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(fht_gbps / HBM_PEAK_GBPS, 4),
