@@ -170,3 +170,33 @@ def test_plan_replays_match_direct_calls(orc):
     (a, b), = splan.results
     assert int(host(a)[0]) == want_s and host(b).tolist() == want_x.tolist()
     splan.destroy()
+
+
+def test_plan_with_scanned_windows(orc):
+    """A plan whose jobs take the scanned windows (angle form, a large bound,
+    no bound) and a tall two-pass band, replayed twice, against the oracle."""
+    import math
+    from paper_1912_01884_amd import fhtp
+    dev = require_gpu()
+    rng = np.random.default_rng([191201884, 77, 1])
+    shapes = [(256, 300, 8), (1024, 200, 4), (512, 130, 2)]
+    imgs = [rng.integers(0, 256, size=(h, w)).astype(np.uint8) for h, w, _ in shapes]
+    ks = [k for _, _, k in shapes]
+    gammas = [math.radians(10), None, None]
+    bends = [None, 40, 1000]
+    plan = fhtp.Plan([to_device(im, dev) for im in imgs], ks, bends=bends, gammas=gammas)
+    want = []
+    for im, k, b, g in zip(imgs, ks, bends, gammas):
+        want.append(orc.detect_polyline(im, k, gamma=g) if g is not None
+                    else orc.detect_polyline(im, k, bend=b))
+    for rep in range(2):
+        for a, b in plan.results:
+            a.fill_(-7)
+            b.fill_(-7)
+        announce(f"plan with scanned windows: replay {rep}")
+        plan.launch()
+        torch.cuda.synchronize()
+        for (a, b), (w_s, w_x) in zip(plan.results, want):
+            assert int(host(a)[0]) == w_s, rep
+            assert host(b).tolist() == w_x.tolist(), rep
+    plan.destroy()
