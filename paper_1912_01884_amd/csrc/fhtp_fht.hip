@@ -338,7 +338,27 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
             fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[jn], nx - pk.job[jn].item0, tid, pre);
         }
 
-        fht_stages<N, 1, P, C::LW, C::PREFETCH>(v, lds, tid);
+        if constexpr (sizeof(PixT) == 1 && P >= 2) {
+            // Stages 1 .. p-1 never mix the top and bottom halves of the
+            // block, and apply the same shifts to both.  With 8-bit pixels a
+            // half's sums stay below 2^16 (at most 64 * 255), so row y and row
+            // y + n/2 share a register (low and high 16 bits, no carry between
+            // them) and those stages run as the recursion of a block of n/2
+            // rows on n/2 registers: half the LDS exchange and half the adds.
+            constexpr int H = N / 2;
+            int32_t pk[H];
+#pragma unroll
+            for (int y = 0; y < H; ++y) pk[y] = v[y] | (v[y + H] << 16);
+            fht_stages<H, 1, P - 1, C::LW, C::PREFETCH>(pk, lds, tid);
+#pragma unroll
+            for (int t = 0; t < H; ++t) {
+                v[t] = pk[t] & 0xffff;
+                v[t + H] = (int32_t)((uint32_t)pk[t] >> 16);
+            }
+            fht_stages<N, P, P, C::LW, C::PREFETCH>(v, lds, tid);  // the last stage, unpacked
+        } else {
+            fht_stages<N, 1, P, C::LW, C::PREFETCH>(v, lds, tid);
+        }
         fht_store<P>(J, local, tid, v);
         item = next;
     }

@@ -53,6 +53,9 @@ TABLE_CASES = [
     (256, 700, 2, np.uint8, None),    # several tiles per band
     (512, 900, 4, np.uint16, "sat"),  # saturated
     (64, 2000, 2, np.uint8, "sat"),
+    (128, 300, 1, np.uint8, "sat"),   # 8-bit, n = 128: the largest packed half-band sums
+    (256, 100, 1, np.uint8, "sat"),   # 8-bit two-pass sub-blocks, saturated
+    (128 * 3, 517, 3, np.uint8, None),
 ]
 
 
