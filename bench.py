@@ -30,8 +30,8 @@ HBM_PEAK_GBPS = 8000.0
 # then WRITE_SIZE), each scaled by what the same counter reads for a copy of a
 # known size in the same run.  Valid only for the kernel source they were
 # taken on (sha256 of csrc/fhtp_fht.hip); otherwise the traffic is unknown.
-FHT_TRAFFIC = {"source_sha256": "cdac1114378378f7aa191d74cb694334aabca5a632807fc827e676ba11e8b4d3",
-               "fetch_bytes": 36059484, "write_bytes": 140754944}
+FHT_TRAFFIC = {"source_sha256": "167a93ff5aa95c2877526d1082868baa62d24590006d9f8a8740faea205fa08c",
+               "fetch_bytes": 36200697, "write_bytes": 140754944}
 
 
 def byte_model(h, w, k, bpp):
