@@ -16,8 +16,9 @@
 // Layout on gfx950: one thread owns one c-space column and keeps the n running
 // sums of that column in VGPRs through all p stages; the operand that comes
 // from another column (c + ceil(s/2)) is exchanged through LDS once per
-// stage.  A workgroup of NT threads covers NT columns and produces the
-// NT - (n-1) leftmost of them (the rest are its halo).  Global loads and table
+// stage.  A workgroup of NT threads covers NC columns (its waves overlap by one
+// column) and produces the NC - (n-1) leftmost of them (the rest are its
+// halo).  Global loads and table
 // stores are coalesced along x.  Bands taller than 2^7 rows run the same kernel
 // on 128-row sub-blocks, then a second kernel adds the sub-blocks along the
 // coarse levels of the recursion.
@@ -60,8 +61,16 @@ struct RegCfg {
     static constexpr int N = 1 << P;
     static constexpr int NT = (P >= 7) ? 512 : 256;
     static constexpr int HALF = (N >= 2) ? N / 2 : 1;
-    static constexpr int LW = NT + HALF;               // LDS row width (halo reads stay inside)
-    static constexpr int LDS_WORDS = (N >= 2) ? (N / 2) * LW : 1;
+    // Distinct columns of a workgroup: with P >= 1 the waves overlap by one
+    // column (see from_next_lane), so 63 per wave plus the last wave's lane 63.
+    static constexpr int NC = (P >= 1) ? NT - NT / 64 + 1 : NT;
+    // LDS holds the exchanged operands column by column: (column c, row r) at
+    // c * RW + r.  RW is odd so that the 64 lanes of a wave, one column each,
+    // hit distinct banks.  Reads reach column NC + HALF - 2; column NT + HALF
+    // is the spare written by duplicate lanes.
+    static constexpr int RW = (HALF >= 2) ? HALF + 1 : 1;
+    static constexpr int SPARE = NT + HALF;
+    static constexpr int LDS_WORDS = (N >= 2) ? (SPARE + 1) * RW : 1;
     static constexpr int NPK = (N + 1) / 2;            // packed 16-bit pixel pairs per column
     static constexpr int NDIR = (P == 0) ? 1 : 2;      // one-row bands have only d = 0
     // Fetch the next item's pixels during the current item's stages.  At
@@ -69,22 +78,36 @@ struct RegCfg {
     static constexpr bool PREFETCH = P <= 6;
 };
 
+// The lower operands of shifts 2t and 2t+1 of one stage are the same lower-
+// block sum T(2b+1, ., t) at columns c + t and c + t + 1 (ceil(s/2) in the
+// recursion above).  A lane reads only the first from LDS and takes the second
+// from lane + 1 of its wave with a DPP wave shift (lane 63 receives 0), which
+// halves the LDS reads of a stage.  So that every column has a right
+// neighbour in its own wave, consecutive waves overlap by one column: lane 63
+// of wave q and lane 0 of wave q + 1 hold the same column, only lane 0's copy
+// is kept (the duplicate writes its operands to a spare LDS column that no
+// lane reads, and stores nothing), and the last wave's lane 63 is halo.
+__device__ __forceinline__ int32_t from_next_lane(int32_t x) {
+    return __builtin_amdgcn_mov_dpp(x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+}
+
 // One stage of the recursion on the column held in v, in place: the operands
 // of the lower half-blocks go through LDS, and outputs (2t, 2t+1) overwrite
 // slots that no later t of the same stage still reads (t runs downwards).
-template <int N, int J, int LW>
-__device__ __forceinline__ void fht_stage(int32_t (&v)[N], int32_t* lds, int tid) {
+// `col` is the thread's LDS column for reads, `wcol` the one it writes.
+template <int N, int J, int RW>
+__device__ __forceinline__ void fht_stage(int32_t (&v)[N], int32_t* lds, int col, int wcol) {
     constexpr int half = 1 << (J - 1);
     constexpr int blocks = N >> J;
     // The lane's LDS byte address, made opaque to the optimiser so that per-row
     // addresses are formed next to their use instead of being hoisted out of
     // the loop into one register per row.
-    unsigned int lane_addr = (unsigned int)tid * 4u;
+    unsigned int lane_addr = (unsigned int)(col * RW) * 4u;
     __syncthreads();  // the previous stage's LDS reads are complete
 #pragma unroll
     for (int b = 0; b < blocks; ++b)
 #pragma unroll
-        for (int t = 0; t < half; ++t) lds[(b * half + t) * LW + tid] = v[b * 2 * half + half + t];
+        for (int t = 0; t < half; ++t) lds[wcol * RW + b * half + t] = v[b * 2 * half + half + t];
     __syncthreads();
     // Groups of at most 16 operand pairs, with scheduling barriers between
     // them, so the compiler cannot hoist every LDS read of the stage at once
@@ -99,10 +122,10 @@ __device__ __forceinline__ void fht_stage(int32_t (&v)[N], int32_t* lds, int tid
 #pragma unroll
             for (int t = g * G + G - 1; t >= g * G; --t) {
                 const int32_t a = v[b * 2 * half + t];
-                const int32_t* row =
-                    reinterpret_cast<const int32_t*>(lbase + ((b * half + t) * LW + t) * 4);
-                v[b * 2 * half + 2 * t + 1] = a + row[1];
-                v[b * 2 * half + 2 * t] = a + row[0];
+                const int32_t x =
+                    *reinterpret_cast<const int32_t*>(lbase + (t * RW + b * half + t) * 4);
+                v[b * 2 * half + 2 * t + 1] = a + from_next_lane(x);
+                v[b * 2 * half + 2 * t] = a + x;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -111,15 +134,15 @@ __device__ __forceinline__ void fht_stage(int32_t (&v)[N], int32_t* lds, int tid
 
 // The same stage with no scheduling constraints: the compiler may issue all
 // LDS reads of the stage together (more registers, more memory parallelism).
-template <int N, int J, int LW>
-__device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, int tid) {
+template <int N, int J, int RW>
+__device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, int col, int wcol) {
     constexpr int half = 1 << (J - 1);
     constexpr int blocks = N >> J;
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < blocks; ++b)
 #pragma unroll
-        for (int t = 0; t < half; ++t) lds[(b * half + t) * LW + tid] = v[b * 2 * half + half + t];
+        for (int t = 0; t < half; ++t) lds[wcol * RW + b * half + t] = v[b * 2 * half + half + t];
     __syncthreads();
     int32_t nv[N];
 #pragma unroll
@@ -127,23 +150,23 @@ __device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, in
 #pragma unroll
         for (int t = 0; t < half; ++t) {
             const int32_t a = v[b * 2 * half + t];
-            const int32_t* row = lds + (b * half + t) * LW + tid + t;
-            nv[b * 2 * half + 2 * t] = a + row[0];
-            nv[b * 2 * half + 2 * t + 1] = a + row[1];
+            const int32_t x = lds[(col + t) * RW + b * half + t];
+            nv[b * 2 * half + 2 * t] = a + x;
+            nv[b * 2 * half + 2 * t + 1] = a + from_next_lane(x);
         }
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) v[q] = nv[q];
 }
 
-template <int N, int J, int P, int LW, bool GROUPED>
-__device__ __forceinline__ void fht_stages(int32_t (&v)[N], int32_t* lds, int tid) {
+template <int N, int J, int P, int RW, bool GROUPED>
+__device__ __forceinline__ void fht_stages(int32_t (&v)[N], int32_t* lds, int col, int wcol) {
     if constexpr (J <= P) {
         if constexpr (GROUPED)
-            fht_stage<N, J, LW>(v, lds, tid);
+            fht_stage<N, J, RW>(v, lds, col, wcol);
         else
-            fht_stage_free<N, J, LW>(v, lds, tid);
-        fht_stages<N, J + 1, P, LW, GROUPED>(v, lds, tid);
+            fht_stage_free<N, J, RW>(v, lds, col, wcol);
+        fht_stages<N, J + 1, P, RW, GROUPED>(v, lds, col, wcol);
     }
 }
 
@@ -199,7 +222,7 @@ struct FhtItem {
 // left in the image) in reverse, so consecutive items read overlapping image
 // columns: right tile t and left tile tiles-1-t share most of their pixels.
 template <int NDIR>
-__device__ __forceinline__ FhtItem fht_decode(const FhtJob& J, int local, int tid) {
+__device__ __forceinline__ FhtItem fht_decode(const FhtJob& J, int local, int col) {
     FhtItem it;
     const int per_blk = NDIR * J.tiles;
     it.blk = local / per_blk;
@@ -207,7 +230,7 @@ __device__ __forceinline__ FhtItem fht_decode(const FhtJob& J, int local, int ti
     it.dir = NDIR == 2 ? (u & 1) : 0;
     const int t = NDIR == 2 ? (u >> 1) : u;
     const int tile = it.dir ? J.tiles - 1 - t : t;
-    it.c = tile * J.T + tid;
+    it.c = tile * J.T + col;
     const int cm = it.c % J.W;
     it.ximg = it.dir == 0 ? cm : (J.W - 1 - cm);
     it.inside = it.ximg < J.w;
@@ -218,9 +241,9 @@ __device__ __forceinline__ FhtItem fht_decode(const FhtJob& J, int local, int ti
 // base is uniform (scalar registers), rows are scalar offsets, and the column
 // is one 32-bit lane offset shared by every row.
 template <int N, int NPK, int NDIR, typename PixT>
-__device__ __forceinline__ void fetch_column(const FhtJob& J, int local, int tid,
+__device__ __forceinline__ void fetch_column(const FhtJob& J, int local, int col,
                                              uint32_t (&pk)[NPK]) {
-    const FhtItem it = fht_decode<NDIR>(J, local, tid);
+    const FhtItem it = fht_decode<NDIR>(J, local, col);
     const PixT* img = static_cast<const PixT*>(J.img);
     const unsigned int row_bytes = (unsigned int)J.w * sizeof(PixT);
     const __amdgpu_buffer_rsrc_t r =
@@ -237,9 +260,9 @@ __device__ __forceinline__ void fetch_column(const FhtJob& J, int local, int tid
 
 // Same pixels straight into the running-sum registers (no prefetch).
 template <int N, int NDIR, typename PixT>
-__device__ __forceinline__ void fetch_column_direct(const FhtJob& J, int local, int tid,
+__device__ __forceinline__ void fetch_column_direct(const FhtJob& J, int local, int col,
                                                     int32_t (&v)[N]) {
-    const FhtItem it = fht_decode<NDIR>(J, local, tid);
+    const FhtItem it = fht_decode<NDIR>(J, local, col);
     const PixT* img = static_cast<const PixT*>(J.img);
     const unsigned int row_bytes = (unsigned int)J.w * sizeof(PixT);
     const __amdgpu_buffer_rsrc_t r =
@@ -254,13 +277,13 @@ __device__ __forceinline__ void fetch_column_direct(const FhtJob& J, int local, 
 //   to_table: tables[blk][n-1 +- s][x] of a band of n = 2^P rows (d = 0 only from dir 0);
 //   else:     scratch[(blk*2 + dir)*2^P + s][c] in c-space (pass 1 of tall bands).
 template <int P>
-__device__ __forceinline__ void fht_store(const FhtJob& J, int local, int tid,
+__device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
                                           const int32_t (&v)[1 << P]) {
     using C = RegCfg<P>;
     constexpr int N = C::N;
-    const FhtItem it = fht_decode<C::NDIR>(J, local, tid);
+    const FhtItem it = fht_decode<C::NDIR>(J, local, col);
     const int W = J.W;
-    if (tid >= J.T || it.c >= W) return;
+    if (col >= J.T || it.c >= W) return;
     const unsigned int row_bytes = (unsigned int)W * 4u;
     if (J.to_table) {
         constexpr int D = 2 * N - 1;
@@ -293,7 +316,7 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int tid,
 // Work item = (run, row block, direction, column tile).  Prefetching variants
 // loop over items with a stride of the grid, fetching the next item's pixels
 // while the current one runs its stages; the others take one item per
-// workgroup.  A tile produces T columns (T <= NT - (n-1)); the rest of its NT
+// workgroup.  A tile produces T columns (T <= NC - (n-1)); the rest of its NC
 // columns are halo.
 template <int P, typename PixT, int CAP>
 __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk) {
@@ -302,6 +325,10 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
     __shared__ int32_t lds[C::LDS_WORDS];
     const int tid = threadIdx.x;
     const int total = pk.total;
+    // The thread's column within the tile: 63 per wave (waves overlap by one).
+    const int col = P >= 1 ? tid - (tid >> 6) : tid;
+    const bool wr = P == 0 || (tid & 63) != 63 || tid == C::NT - 1;  // not a duplicate
+    const int wcol = wr ? col : C::SPARE;
 
     uint32_t pre[C::NPK];
     // Workgroups are spread over the XCDs round-robin (workgroup b on XCD
@@ -314,7 +341,7 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
     }
     if constexpr (C::PREFETCH) {
         const int j = fht_find_job(pk, item);
-        fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[j], item - pk.job[j].item0, tid, pre);
+        fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[j], item - pk.job[j].item0, col, pre);
     }
     while (item < total) {
         const int j = fht_find_job(pk, item);
@@ -328,14 +355,14 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
                 if (2 * q + 1 < N) v[2 * q + 1] = (int32_t)(pre[q] >> 16);
             }
         } else {
-            fetch_column_direct<N, C::NDIR, PixT>(J, local, tid, v);
+            fetch_column_direct<N, C::NDIR, PixT>(J, local, col, v);
         }
         const int next = item + (int)gridDim.x;
         if constexpr (C::PREFETCH) {
             // Unconditional prefetch (the last round re-reads its own item).
             const int nx = next < total ? next : item;
             const int jn = fht_find_job(pk, nx);
-            fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[jn], nx - pk.job[jn].item0, tid, pre);
+            fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[jn], nx - pk.job[jn].item0, col, pre);
         }
 
         if constexpr (sizeof(PixT) == 1 && P >= 2) {
@@ -349,17 +376,17 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
             int32_t pk[H];
 #pragma unroll
             for (int y = 0; y < H; ++y) pk[y] = v[y] | (v[y + H] << 16);
-            fht_stages<H, 1, P - 1, C::LW, C::PREFETCH>(pk, lds, tid);
+            fht_stages<H, 1, P - 1, C::RW, C::PREFETCH>(pk, lds, col, wcol);
 #pragma unroll
             for (int t = 0; t < H; ++t) {
                 v[t] = pk[t] & 0xffff;
                 v[t + H] = (int32_t)((uint32_t)pk[t] >> 16);
             }
-            fht_stages<N, P, P, C::LW, C::PREFETCH>(v, lds, tid);  // the last stage, unpacked
+            fht_stages<N, P, P, C::RW, C::PREFETCH>(v, lds, col, wcol);  // the last stage, unpacked
         } else {
-            fht_stages<N, 1, P, C::LW, C::PREFETCH>(v, lds, tid);
+            fht_stages<N, 1, P, C::RW, C::PREFETCH>(v, lds, col, wcol);
         }
-        fht_store<P>(J, local, tid, v);
+        if (wr) fht_store<P>(J, local, col, v);
         item = next;
     }
 }
@@ -484,7 +511,7 @@ hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
             occ = 1;
         occupancy = occ;
     }
-    const int Tmax = C::NT - (C::N - 1);
+    const int Tmax = C::NC - (C::N - 1);
     FhtPack<CAP> pk{};
     long long total = 0;
     for (int q = 0; q < count; ++q) {
