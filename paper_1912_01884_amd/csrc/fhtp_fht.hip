@@ -313,10 +313,11 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
     }
 }
 
-// Work item = (run, row block, direction, column tile).  Prefetching variants
-// loop over items with a stride of the grid, fetching the next item's pixels
-// while the current one runs its stages; the others take one item per
-// workgroup.  A tile produces T columns (T <= NC - (n-1)); the rest of its NC
+// Work item = (run, row block, direction, column tile).  The grid holds as
+// many workgroups as the chip keeps resident and loops over the items, so a
+// workgroup's table stores drain while it loads and transforms its next item;
+// the prefetching variants also fetch the next item's pixels while the
+// current one runs its stages.  A tile produces T columns (T <= NC - (n-1)); the rest of its NC
 // columns are halo.
 template <int P, typename PixT, int CAP>
 __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk) {
@@ -332,18 +333,23 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
 
     uint32_t pre[C::NPK];
     // Workgroups are spread over the XCDs round-robin (workgroup b on XCD
-    // b % 8).  When the grid covers every item, give each XCD a contiguous run
-    // of items instead, so the tiles that share pixel columns meet in one L2.
-    int item = blockIdx.x;
-    if ((int)gridDim.x == total) {
-        const int xcd = item % kXcds, slot = item / kXcds;
-        item = xcd * (total / kXcds) + min(xcd, total % kXcds) + slot;
-    }
+    // b % 8).  Each XCD is given a contiguous run of items instead, so the
+    // tiles that share pixel columns meet in one L2: slot i of the launch
+    // (workgroup i % grid, round i / grid) takes item xmap(i), which lies in
+    // the run of XCD i % 8 whenever the grid is a multiple of 8 or covers
+    // every item in one round.
+    auto xmap = [total](int i) {
+        const int xcd = i % kXcds, slot = i / kXcds;
+        return xcd * (total / kXcds) + min(xcd, total % kXcds) + slot;
+    };
+    const int grid = (int)gridDim.x;
+    int vi = blockIdx.x;
+    int item = xmap(vi);
     if constexpr (C::PREFETCH) {
         const int j = fht_find_job(pk, item);
         fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[j], item - pk.job[j].item0, col, pre);
     }
-    while (item < total) {
+    while (vi < total) {
         const int j = fht_find_job(pk, item);
         const FhtJob& J = pk.job[j];
         const int local = item - J.item0;
@@ -357,10 +363,10 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
         } else {
             fetch_column_direct<N, C::NDIR, PixT>(J, local, col, v);
         }
-        const int next = item + (int)gridDim.x;
+        vi += grid;
         if constexpr (C::PREFETCH) {
             // Unconditional prefetch (the last round re-reads its own item).
-            const int nx = next < total ? next : item;
+            const int nx = vi < total ? xmap(vi) : item;
             const int jn = fht_find_job(pk, nx);
             fetch_column<N, C::NPK, C::NDIR, PixT>(pk.job[jn], nx - pk.job[jn].item0, col, pre);
         }
@@ -387,7 +393,7 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
             fht_stages<N, 1, P, C::RW, C::PREFETCH>(v, lds, col, wcol);
         }
         if (wr) fht_store<P>(J, local, col, v);
-        item = next;
+        if (vi < total) item = xmap(vi);
     }
 }
 
@@ -534,7 +540,7 @@ hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
     pk.count = count;
     pk.total = (int)total;
     if (total == 0) return hipSuccess;
-    const long long slots = C::PREFETCH ? (long long)occupancy * device_cus() : total;
+    const long long slots = (long long)occupancy * device_cus();
     const int grid = (int)(total < slots ? total : slots);
     hipLaunchKernelGGL((fht_reg_kernel<P, PixT, CAP>), dim3(grid), dim3(C::NT), 0, stream, pk);
     return hipGetLastError();
