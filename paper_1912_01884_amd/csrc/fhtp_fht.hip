@@ -16,8 +16,8 @@
 // Layout on gfx950: one thread owns one c-space column and keeps the n running
 // sums of that column in VGPRs through all p stages; the operand that comes
 // from another column (c + ceil(s/2)) is exchanged through LDS once per
-// stage.  A workgroup of NT threads covers NC columns (its waves overlap by one
-// column) and produces the NC - (n-1) leftmost of them (the rest are its
+// stage.  A workgroup of NT threads covers NC columns (its waves overlap by a
+// few columns) and produces the NC - (n-1) leftmost of them (the rest are its
 // halo).  Global loads and table
 // stores are coalesced along x.  Bands taller than 2^7 rows run the same kernel
 // on 128-row sub-blocks, then a second kernel adds the sub-blocks along the
@@ -56,14 +56,19 @@ __device__ __forceinline__ uint32_t buffer_pixel(__amdgpu_buffer_rsrc_t r, unsig
         return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
 }
 
+// Stages 1 .. kLaneStages take their operands from lanes + 1 .. + 2^(J-1) of
+// the wave instead of LDS (stage J reads columns c .. c + 2^(J-1)).
+constexpr int kLaneStages = 2;
+
 template <int P>
 struct RegCfg {
     static constexpr int N = 1 << P;
     static constexpr int NT = (P >= 7) ? 512 : 256;
     static constexpr int HALF = (N >= 2) ? N / 2 : 1;
-    // Distinct columns of a workgroup: with P >= 1 the waves overlap by one
-    // column (see from_next_lane), so 63 per wave plus the last wave's lane 63.
-    static constexpr int NC = (P >= 1) ? NT - NT / 64 + 1 : NT;
+    // Distinct columns of a workgroup: consecutive waves overlap by K columns
+    // (see from_next_lane), so 64 - K per wave plus the last wave's K.
+    static constexpr int K = (P >= 1) ? (1 << kLaneStages) - 1 : 0;
+    static constexpr int NC = NT - (NT / 64 - 1) * K;
     // LDS holds the exchanged operands column by column: (column c, row r) at
     // c * RW + r.  RW is odd so that the 64 lanes of a wave, one column each,
     // hit distinct banks.  Reads reach column NC + HALF - 2; column NT + HALF
@@ -82,11 +87,12 @@ struct RegCfg {
 // block sum T(2b+1, ., t) at columns c + t and c + t + 1 (ceil(s/2) in the
 // recursion above).  A lane reads only the first from LDS and takes the second
 // from lane + 1 of its wave with a DPP wave shift (lane 63 receives 0), which
-// halves the LDS reads of a stage.  So that every column has a right
-// neighbour in its own wave, consecutive waves overlap by one column: lane 63
-// of wave q and lane 0 of wave q + 1 hold the same column, only lane 0's copy
-// is kept (the duplicate writes its operands to a spare LDS column that no
-// lane reads, and stores nothing), and the last wave's lane 63 is halo.
+// halves the LDS reads of a stage; the first kLaneStages stages need no LDS
+// at all.  So that the lanes a column reads are in its own wave, consecutive
+// waves overlap by K = 2^kLaneStages - 1 columns: lanes 64 - K .. 63 of wave q
+// hold the columns of lanes 0 .. K - 1 of wave q + 1, only the latter copies
+// are kept (the duplicates write their operands to a spare LDS column that no
+// lane reads, and store nothing), and the last wave's top K lanes are halo.
 __device__ __forceinline__ int32_t from_next_lane(int32_t x) {
     return __builtin_amdgcn_mov_dpp(x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
 }
@@ -161,7 +167,28 @@ __device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, in
 
 template <int N, int J, int P, int RW, bool GROUPED>
 __device__ __forceinline__ void fht_stages(int32_t (&v)[N], int32_t* lds, int col, int wcol) {
-    if constexpr (J <= P) {
+    if constexpr (J <= P && J <= kLaneStages) {
+        // Shifts 2t and 2t+1 add the lower block's shift t at columns c + t and
+        // c + t + 1, i.e. lanes + t and + t + 1: moved by wave shifts, with no
+        // LDS exchange and no barrier (the next LDS stage opens with one).
+        constexpr int half = 1 << (J - 1);
+#pragma unroll
+        for (int b = 0; b < (N >> J); ++b) {
+            int32_t o[2 * half];
+#pragma unroll
+            for (int t = 0; t < half; ++t) {
+                const int32_t a = v[b * 2 * half + t];
+                int32_t x = v[b * 2 * half + half + t];
+#pragma unroll
+                for (int q = 0; q < t; ++q) x = from_next_lane(x);
+                o[2 * t] = a + x;
+                o[2 * t + 1] = a + from_next_lane(x);
+            }
+#pragma unroll
+            for (int q = 0; q < 2 * half; ++q) v[b * 2 * half + q] = o[q];
+        }
+        fht_stages<N, J + 1, P, RW, GROUPED>(v, lds, col, wcol);
+    } else if constexpr (J <= P) {
         if constexpr (GROUPED)
             fht_stage<N, J, RW>(v, lds, col, wcol);
         else
@@ -317,8 +344,8 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
 // many workgroups as the chip keeps resident and loops over the items, so a
 // workgroup's table stores drain while it loads and transforms its next item;
 // the prefetching variants also fetch the next item's pixels while the
-// current one runs its stages.  A tile produces T columns (T <= NC - (n-1)); the rest of its NC
-// columns are halo.
+// current one runs its stages.  A tile produces T columns (T <= NC - (n-1));
+// the rest of its NC columns are halo.
 template <int P, typename PixT, int CAP>
 __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk) {
     using C = RegCfg<P>;
@@ -326,9 +353,9 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
     __shared__ int32_t lds[C::LDS_WORDS];
     const int tid = threadIdx.x;
     const int total = pk.total;
-    // The thread's column within the tile: 63 per wave (waves overlap by one).
-    const int col = P >= 1 ? tid - (tid >> 6) : tid;
-    const bool wr = P == 0 || (tid & 63) != 63 || tid == C::NT - 1;  // not a duplicate
+    // The thread's column within the tile (waves overlap by K columns).
+    const int col = (tid >> 6) * (64 - C::K) + (tid & 63);
+    const bool wr = (tid & 63) < 64 - C::K || (tid >> 6) == C::NT / 64 - 1;  // not a duplicate
     const int wcol = wr ? col : C::SPARE;
 
     uint32_t pre[C::NPK];

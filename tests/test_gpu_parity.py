@@ -56,6 +56,12 @@ TABLE_CASES = [
     (128, 300, 1, np.uint8, "sat"),   # 8-bit, n = 128: the largest packed half-band sums
     (256, 100, 1, np.uint8, "sat"),   # 8-bit two-pass sub-blocks, saturated
     (128 * 3, 517, 3, np.uint8, None),
+    # short bands over several waves and tiles (the waves of a tile overlap by
+    # a few columns, the first stages move operands between lanes)
+    (8, 700, 4, np.uint16, None),     # n = 2
+    (16, 600, 4, np.uint8, "sat"),    # n = 4
+    (64, 900, 8, np.uint16, None),    # n = 8
+    (64, 530, 4, np.uint8, None),     # n = 16
 ]
 
 
