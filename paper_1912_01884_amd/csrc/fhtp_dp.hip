@@ -1002,23 +1002,28 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
         const int x3 = min(max(xn + c1 + c2 - 2 * (n - 1), 0), w - 1);
         s2[u] = P3[(unsigned int)c2 * pitch + (unsigned int)x3];
     }
+    // No branch until every load of the round trip has been issued and used:
+    // an early exit here would let the compiler sink the candidate loads
+    // behind the first one, two memory latencies per trip instead of one.
     const int l1 = rn - (r - B);
-    if ((unsigned)l1 >= (unsigned)L1 || rn >= D) return false;
-    if (lane == 0) a.xs[i + 1] = xn;
+    const bool ok1 = (unsigned)l1 < (unsigned)L1 && rn < D;
     const int xnn = xn + rn - (n - 1);
-    if (xnn < 0 || xnn >= w) return false;
-    const int r2 = __shfl(s1, l1, 64);
+    const int r2 = __shfl(s1, l1 & 63, 64);
     const int l2s = r2 - (rn - B);
-    if ((unsigned)l2s >= (unsigned)L1 || r2 < 0 || r2 >= D) return false;
-    if (lane == 0) a.xs[i + 2] = xnn;
+    const bool ok2 = ok1 && xnn >= 0 && xnn < w && (unsigned)l2s < (unsigned)L1 && r2 >= 0 && r2 < D;
     const int x3 = xnn + r2 - (n - 1);
-    if (x3 < 0 || x3 >= w) return false;
+    const bool ok3 = ok2 && x3 >= 0 && x3 < w;
     const int slot = l1 >> 1;
     int mine = s2[0];
 #pragma unroll
     for (int u = 1; u < U; ++u) mine = slot == u ? s2[u] : mine;
-    const int r3 = __shfl(mine, ((l1 & 1) << 5) | l2s, 64);
-    if (lane == 0) a.xs[i + 3] = x3;
+    const int r3 = __shfl(mine, ((l1 & 1) << 5) | (l2s & 31), 64);
+    if (lane == 0) {
+        if (ok1) a.xs[i + 1] = xn;
+        if (ok2) a.xs[i + 2] = xnn;
+        if (ok3) a.xs[i + 3] = x3;
+    }
+    if (!ok3) return false;
     x = x3;
     r = r3;
     i += 3;
