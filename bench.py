@@ -30,8 +30,8 @@ HBM_PEAK_GBPS = 8000.0
 # then WRITE_SIZE), each scaled by what the same counter reads for a copy of a
 # known size in the same run.  Valid only for the kernel source they were
 # taken on (sha256 of csrc/fhtp_fht.hip); otherwise the traffic is unknown.
-FHT_TRAFFIC = {"source_sha256": "167a93ff5aa95c2877526d1082868baa62d24590006d9f8a8740faea205fa08c",
-               "fetch_bytes": 36200697, "write_bytes": 140754944}
+FHT_TRAFFIC = {"source_sha256": "82b19cc414cc9bc5a1908518d4fb4267bd03744b7ddb1b89c71840d5dd203088",
+               "fetch_bytes": 47690859, "write_bytes": 163054208}
 
 
 def byte_model(h, w, k, bpp):
