@@ -140,6 +140,9 @@ __device__ __forceinline__ void fht_stage(int32_t (&v)[N], int32_t* lds, int col
 
 // The same stage with no scheduling constraints: the compiler may issue all
 // LDS reads of the stage together (more registers, more memory parallelism).
+// In place, t downwards as above: a second array for the outputs made the
+// compiler spill registers at n = 128 (their scratch traffic showed up as
+// extra HBM writes).
 template <int N, int J, int RW>
 __device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, int col, int wcol) {
     constexpr int half = 1 << (J - 1);
@@ -150,19 +153,16 @@ __device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, in
 #pragma unroll
         for (int t = 0; t < half; ++t) lds[wcol * RW + b * half + t] = v[b * 2 * half + half + t];
     __syncthreads();
-    int32_t nv[N];
 #pragma unroll
     for (int b = 0; b < blocks; ++b) {
 #pragma unroll
-        for (int t = 0; t < half; ++t) {
+        for (int t = half - 1; t >= 0; --t) {
             const int32_t a = v[b * 2 * half + t];
             const int32_t x = lds[(col + t) * RW + b * half + t];
-            nv[b * 2 * half + 2 * t] = a + x;
-            nv[b * 2 * half + 2 * t + 1] = a + from_next_lane(x);
+            v[b * 2 * half + 2 * t + 1] = a + from_next_lane(x);
+            v[b * 2 * half + 2 * t] = a + x;
         }
     }
-#pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = nv[q];
 }
 
 template <int N, int J, int P, int RW, bool GROUPED>
