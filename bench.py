@@ -30,8 +30,8 @@ HBM_PEAK_GBPS = 8000.0
 # then WRITE_SIZE), each scaled by what the same counter reads for a copy of a
 # known size in the same run.  Valid only for the kernel source they were
 # taken on (sha256 of csrc/fhtp_fht.hip); otherwise the traffic is unknown.
-FHT_TRAFFIC = {"source_sha256": "82b19cc414cc9bc5a1908518d4fb4267bd03744b7ddb1b89c71840d5dd203088",
-               "fetch_bytes": 47690859, "write_bytes": 163054208}
+FHT_TRAFFIC = {"source_sha256": "7b1ac4b7416bda6e4842dd87714b9d40e083681e4821b0d889f36885ddba7dc4",
+               "fetch_bytes": 46931312, "write_bytes": 151025472}
 
 
 def byte_model(h, w, k, bpp):
