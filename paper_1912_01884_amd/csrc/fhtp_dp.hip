@@ -986,7 +986,7 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
     const AT* P1 = static_cast<const AT*>(a.a_base) + (size_t)(i - 1) * a.a_plane;  // A_{i+1}
     const AT* P2 = P1 + a.a_plane;                                                  // A_{i+2}
     const AT* P3 = P2 + a.a_plane;                                                  // A_{i+3}
-    const int rn = P1[(unsigned int)r * pitch + (unsigned int)xn];
+    const int rn_v = P1[(unsigned int)r * pitch + (unsigned int)xn];
     int s1;
     {
         const int c1 = min(max(r - B + lane, 0), D - 1);
@@ -1005,10 +1005,14 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
     // No branch until every load of the round trip has been issued and used:
     // an early exit here would let the compiler sink the candidate loads
     // behind the first one, two memory latencies per trip instead of one.
+    // Every lane loaded the same pointer: as a wave-uniform value it lets the
+    // candidates be picked by v_readlane with a scalar lane index rather than
+    // by a permute through the LDS unit.
+    const int rn = __builtin_amdgcn_readfirstlane(rn_v);
     const int l1 = rn - (r - B);
     const bool ok1 = (unsigned)l1 < (unsigned)L1 && rn < D;
     const int xnn = xn + rn - (n - 1);
-    const int r2 = __shfl(s1, l1 & 63, 64);
+    const int r2 = __builtin_amdgcn_readlane(s1, l1 & 63);
     const int l2s = r2 - (rn - B);
     const bool ok2 = ok1 && xnn >= 0 && xnn < w && (unsigned)l2s < (unsigned)L1 && r2 >= 0 && r2 < D;
     const int x3 = xnn + r2 - (n - 1);
@@ -1017,7 +1021,7 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
     int mine = s2[0];
 #pragma unroll
     for (int u = 1; u < U; ++u) mine = slot == u ? s2[u] : mine;
-    const int r3 = __shfl(mine, ((l1 & 1) << 5) | (l2s & 31), 64);
+    const int r3 = __builtin_amdgcn_readlane(mine, ((l1 & 1) << 5) | (l2s & 31));
     if (lane == 0) {
         if (ok1) a.xs[i + 1] = xn;
         if (ok2) a.xs[i + 2] = xnn;
@@ -1110,7 +1114,7 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
                 return;
             }
             const AT* Pi = A + (size_t)(i - 1) * a.a_plane;
-            const int rn = Pi[(unsigned int)r * pitch + (unsigned int)xn];
+            const int rn_v = Pi[(unsigned int)r * pitch + (unsigned int)xn];
             const bool two = (i + 2 < k) && D <= 256;
             int spec[4];
             if (two) {
@@ -1124,6 +1128,7 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
                     spec[j] = ok ? v : 0;
                 }
             }
+            const int rn = __builtin_amdgcn_readfirstlane(rn_v);  // the same in every lane
             if (rn >= D) {
                 if (lane == 0) *a.score = -1;
                 return;
@@ -1137,7 +1142,7 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
                 }
                 const int slot = rn >> 6;
                 const int mine = slot == 0 ? spec[0] : slot == 1 ? spec[1] : slot == 2 ? spec[2] : spec[3];
-                const int r2 = __shfl(mine, rn & 63, 64);
+                const int r2 = __builtin_amdgcn_readlane(mine, rn & 63);
                 if (lane == 0) a.xs[i + 2] = xnn;
                 x = xnn;
                 r = r2;
