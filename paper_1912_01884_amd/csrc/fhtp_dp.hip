@@ -110,6 +110,10 @@ struct WalkJob {
     int n_keys, a_pitch;
     int n, w, k;
     int bound, full;
+    // Bands 1 .. pair_top were made two per launch (0: none).  For odd i <
+    // pair_top, plane i holds, at the cell (d_i, x_{i+1}) of plane i-1, the link
+    // d_{i+2} that follows d_{i+1}: both links of a pair are read at one index.
+    int pair_top;
 };
 
 template <int CAP>
@@ -573,9 +577,11 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
 //   phase 1: V_{i+1}(x', d') for x' in its 64 columns and d' in its rows
 //            widened by B, into LDS, as the step for band i+1 computes them
 //            (successor column x'' = x' + d', window of V_{i+2} in that
-//            column); the back-pointers A_{i+2} of the cells in its own rows
-//            go to memory;
-//   phase 2: step i from LDS, writing V_i and A_{i+1}.
+//            column), each with the row of its own window maximum;
+//   phase 2: step i from LDS, writing V_i, A_{i+1}, and in the A_{i+2} plane,
+//            at the same cell of step i, the link after next: the choice of
+//            band i+1 for the V_{i+1} cell that band i chose.  The walk reads
+//            both links of a pair at one index.
 //
 // V_{i+1} then never goes through memory and the chain of dependent launches
 // is half as long.  The cells of the widened rows are recomputed by the
@@ -592,7 +598,7 @@ struct DpPairJob {
     const int32_t* h1;   // H_{i+1}
     const int32_t* h0;   // H_i
     int32_t* vout;       // V_i
-    void* a1;            // A_{i+2} plane
+    void* a1;            // A_{i+2} plane: at each cell of step i, the link after next
     void* a0;            // A_{i+1} plane
     int vin_pitch, h_pitch, v_pitch, a_pitch;
     int n, w, items_x, items_y;
@@ -626,6 +632,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     constexpr int LP = kStrip - 1;         // padding on either side of an LDS row
     constexpr int LWP = 64 + 2 * LP;       // strip cells outside the tile land in the padding
     __shared__ int mid[NS * kStrip][LWP];  // V_{i+1}(X0 + c, row m0 + q) at [q][LP + c]
+    __shared__ AT nxt[NS * kStrip][LWP];   // row of that cell's window maximum (its choice)
 
     // Workgroup b runs on XCD b % 8.  Each XCD gets a contiguous run of items
     // instead, an image's items in stripes of kStripeTiles column tiles (every
@@ -676,10 +683,9 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         hv0[j] = __builtin_amdgcn_raw_buffer_load_b32(h0v.rs, (int)(h0b + j * (hp - 4u)), 0, 0);
 
     // Phase 1.  Views: V_{i+2} rows [m0 - B, m0 + NS*kStrip + B), H_{i+1} rows
-    // [m0, m0 + RM), A_{i+2} rows [r0, r0 + kPairRows), each clipped to [0, D).
+    // [m0, m0 + RM), each clipped to [0, D).
     const RowView vv = row_view(a.vin, a.vin_pitch, 4, m0 - B, NS * kStrip + 2 * B, D);
     const RowView h1v = row_view(a.h1, a.h_pitch, 4, m0, RM, D);
-    const RowView a1v = row_view(a.a1, a.a_pitch, esz, r0, kPairRows, D);
     const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
     const unsigned int ap = (unsigned int)a.a_pitch * (unsigned int)esz;
     for (int t = threadIdx.x; t < NS * SC; t += 64 * kPairWaves) {
@@ -699,8 +705,8 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         const int jhi = xs_ok ? D - rs : jlo;
         const unsigned int vb = (unsigned int)(rlo - vv.base) * vp + (unsigned int)xs * 4u;
         const unsigned int hb = (unsigned int)(rs - h1v.base) * hp + (unsigned int)(X0 + c) * 4u;
-        const unsigned int ab = (unsigned int)(rs - a1v.base) * ap + (unsigned int)xs * (unsigned int)esz;
         int* lrow = &mid[q0][LP + c];
+        AT* nrow = &nxt[q0][LP + c];
         // A wave whose every load and cell is valid takes the unmasked copy.
         const bool inner = qlo <= 0 && qhi >= NV1 && jlo <= 0 && jhi >= kStrip;
         auto strip = [&](auto inner_tag) {
@@ -730,18 +736,8 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
                 const bool live = INNER || (j >= jlo && j < jhi);
                 const int val = live && m[j] >= 0 ? hv[j] + m[j] : -1;
                 lrow[j * (LWP - 1)] = val;
-                // back-pointer of an own row (rows outside [r0, r0 + kPairRows)
-                // fall outside the view and are dropped)
-                const bool put = (INNER || xs_ok) && (unsigned)(c - j) < 64u;
                 const int ra = rs - B + ia[j];  // row of the maximum's d''
-                const unsigned int av = (unsigned int)(INNER || ra >= 0 ? ra : 0);
-                const unsigned int off = put ? ab + j * ap : kOut;
-                if constexpr (sizeof(AT) == 1)
-                    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, a1v.rs, (int)off, 0,
-                                                         kStoreScope);
-                else
-                    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, a1v.rs, (int)off, 0,
-                                                          kStoreScope);
+                nrow[j * (LWP - 1)] = (AT)(INNER || ra >= 0 ? ra : 0);
             }
         };
         if (__builtin_amdgcn_ballot_w64(!inner) == 0)
@@ -760,6 +756,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     int m2[kPairDC], ia2[kPairDC];
     window_max<B, kPairDC>(v2, m2, ia2);
     const RowView aview = row_view(a.a0, a.a_pitch, esz, r2, kPairDC, D);
+    const RowView a2view = row_view(a.a1, a.a_pitch, esz, r2, kPairDC, D);  // links after next
     const RowView oview = row_view(a.vout, a.v_pitch, 4, r2, kPairDC, D);
     const unsigned int op = (unsigned int)a.v_pitch * 4u;
     // cell j: row r2 + j < D; V_i(x, d) at x = xp - d2 - j in [0, w)
@@ -774,11 +771,15 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         const int val = m2[j] >= 0 ? hv0[j] + m2[j] : -1;
         const int ra = r2 - B + ia2[j];
         const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
+        const unsigned int av2 = nxt[wave * kPairDC + ia2[j]][LP + lane];  // the chosen cell's choice
         const unsigned int aoff = cell ? ab2 + j * ap : kOut;
-        if constexpr (sizeof(AT) == 1)
+        if constexpr (sizeof(AT) == 1) {
             __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs, (int)aoff, 0, kStoreScope);
-        else
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av2, a2view.rs, (int)aoff, 0, kStoreScope);
+        } else {
             __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs, (int)aoff, 0, kStoreScope);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av2, a2view.rs, (int)aoff, 0, kStoreScope);
+        }
         __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs, (int)(live ? ob + j * (op - 4u) : kOut),
                                               0, kStoreScope);
     }
@@ -1034,6 +1035,74 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
     return true;
 }
 
+// Four bands in one round trip over two pairs of steps made in one launch
+// each (odd i, i + 3 <= pair_top), windows of at most 31 displacements.  The
+// planes of a pair give both of its links at the index of its lower band's
+// cell, so with x_i and d_i known one load gives d_{i+1} and d_{i+2}, and the
+// next pair's two links are loaded for every candidate (d_{i+1}, d_{i+2}) as in
+// walk_three (lanes 0-31 take the even d_{i+1} of the window, lanes 32-63 the
+// odd ones, U candidates per lane, two planes each).
+template <typename AT, int U>
+__device__ __forceinline__ bool walk_four(const WalkJob& a, int lane, int& x, int& r, int& i) {
+    const int n = a.n, w = a.w, D = 2 * n - 1;
+    const int B = a.bound, L1 = 2 * B + 1;
+    const unsigned int pitch = (unsigned int)a.a_pitch;
+    const int xn = x + r - (n - 1);
+    if (xn < 0 || xn >= w || r < 0 || r >= D) return false;
+    const AT* Q1 = static_cast<const AT*>(a.a_base) + (size_t)(i - 1) * a.a_plane;  // d_{i+1}
+    const AT* Q2 = Q1 + a.a_plane;                                                  // d_{i+2}
+    const AT* Q3 = Q2 + a.a_plane;                                                  // d_{i+3}
+    const AT* Q4 = Q3 + a.a_plane;                                                  // d_{i+4}
+    const unsigned int off = (unsigned int)r * pitch + (unsigned int)xn;
+    const int rn_v = Q1[off], rm_v = Q2[off];
+    const int l2 = lane & 31;
+    int s3[U], s4[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int c1 = r - B + 2 * u + (lane >> 5);
+        const int c2 = min(max(c1 - B + l2, 0), D - 1);
+        const int x3 = min(max(xn + c1 + c2 - 2 * (n - 1), 0), w - 1);
+        const unsigned int o3 = (unsigned int)c2 * pitch + (unsigned int)x3;
+        s3[u] = Q3[o3];
+        s4[u] = Q4[o3];
+    }
+    // As in walk_three: no branch until the loads have been used, and the
+    // pointers every lane loaded alike are taken as wave-uniform values.
+    const int rn = __builtin_amdgcn_readfirstlane(rn_v);
+    const int r2 = __builtin_amdgcn_readfirstlane(rm_v);
+    const int l1 = rn - (r - B);
+    const bool ok1 = (unsigned)l1 < (unsigned)L1 && rn < D;
+    const int xnn = xn + rn - (n - 1);
+    const int l2s = r2 - (rn - B);
+    const bool ok2 = ok1 && xnn >= 0 && xnn < w && (unsigned)l2s < (unsigned)L1 && r2 >= 0 && r2 < D;
+    const int x3 = xnn + r2 - (n - 1);
+    const bool ok3 = ok2 && x3 >= 0 && x3 < w;
+    const int slot = l1 >> 1;
+    int m3 = s3[0], m4 = s4[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) {
+        m3 = slot == u ? s3[u] : m3;
+        m4 = slot == u ? s4[u] : m4;
+    }
+    const int src = ((l1 & 1) << 5) | (l2s & 31);
+    const int r3 = __builtin_amdgcn_readlane(m3, src);
+    const int r4 = __builtin_amdgcn_readlane(m4, src);
+    const int l3 = r3 - (r2 - B);
+    const int x4 = x3 + r3 - (n - 1);
+    const bool ok4 = ok3 && (unsigned)l3 < (unsigned)L1 && r3 >= 0 && r3 < D && x4 >= 0 && x4 < w;
+    if (lane == 0) {
+        if (ok1) a.xs[i + 1] = xn;
+        if (ok2) a.xs[i + 2] = xnn;
+        if (ok3) a.xs[i + 3] = x3;
+        if (ok4) a.xs[i + 4] = x4;
+    }
+    if (!ok4) return false;
+    x = x4;
+    r = r4;
+    i += 4;
+    return true;
+}
+
 // Walk of eq. (5), one wave per image: reduce the workgroup keys of the last
 // step, then follow the back-pointers.  The walk is a chain of dependent
 // loads, so every load is unconditional (clamped index, result masked) and
@@ -1096,6 +1165,43 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
         const bool narrow = !a.full && a.win == nullptr && L1 <= 31;
         int i = 1;
         while (i + 1 < k) {
+            if ((i & 1) && i < a.pair_top) {
+                // a pair of links made in one launch (see WalkJob::pair_top)
+                if (narrow && i + 3 <= a.pair_top) {
+                    const bool ok = L1 <= 7    ? walk_four<AT, 4>(a, lane, x, r, i)
+                                    : L1 <= 11 ? walk_four<AT, 6>(a, lane, x, r, i)
+                                    : L1 <= 17 ? walk_four<AT, 9>(a, lane, x, r, i)
+                                    : L1 <= 23 ? walk_four<AT, 12>(a, lane, x, r, i)
+                                               : walk_four<AT, 16>(a, lane, x, r, i);
+                    if (!ok) {
+                        if (lane == 0) *a.score = -1;
+                        return;
+                    }
+                    continue;
+                }
+                const int xn = x + r - (n - 1);
+                if (xn < 0 || xn >= w || r < 0 || r >= D) {
+                    if (lane == 0) *a.score = -1;
+                    return;
+                }
+                const AT* Pi = A + (size_t)(i - 1) * a.a_plane;
+                const unsigned int off = (unsigned int)r * pitch + (unsigned int)xn;
+                const int rn = __builtin_amdgcn_readfirstlane((int)Pi[off]);
+                const int r2 = __builtin_amdgcn_readfirstlane((int)Pi[a.a_plane + off]);
+                const int xnn = xn + rn - (n - 1);
+                if (rn >= D || xnn < 0 || xnn >= w) {
+                    if (lane == 0) *a.score = -1;
+                    return;
+                }
+                if (lane == 0) {
+                    a.xs[i + 1] = xn;
+                    a.xs[i + 2] = xnn;
+                }
+                x = xnn;
+                r = r2;
+                i += 2;
+                continue;
+            }
             if (narrow && i + 3 < k) {
                 const bool ok = L1 <= 7    ? walk_three<AT, 4>(a, lane, x, r, i)
                                 : L1 <= 11 ? walk_three<AT, 6>(a, lane, x, r, i)
@@ -1448,7 +1554,8 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
 }
 
 template <typename AT, int CAP>
-hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
+hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs,
+                     const std::vector<const DpJobSpec*>& paired, hipStream_t s) {
     for (size_t q0 = 0; q0 < jobs.size(); q0 += CAP) {
         WalkPack<CAP> pk{};
         const int cnt = (int)std::min<size_t>(CAP, jobs.size() - q0);
@@ -1472,6 +1579,9 @@ hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
             a.win = J.plan.kind == WindowKind::Angle ? J.buf.win : nullptr;
             a.score = J.score;
             a.xs = J.xs;
+            // run_steps_paired makes bands 1 .. P - (P & 1) in pairs, P = k - 2
+            const bool in_pairs = std::find(paired.begin(), paired.end(), &J) != paired.end();
+            a.pair_top = in_pairs ? (g.k - 2) - ((g.k - 2) & 1) : 0;
         }
         pk.count = cnt;
         hipLaunchKernelGGL((walk<AT, CAP>), dim3(cnt), dim3(64), 0, s, pk);
@@ -1513,6 +1623,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
     for (const DpJobSpec* J : jobs)
         if (J->g.k >= 2) rest.push_back(J);
     std::vector<bool> done(rest.size(), false);
+    std::vector<const DpJobSpec*> paired_jobs;  // images whose steps went two per launch
     for (size_t q = 0; q < rest.size(); ++q) {
         if (done[q]) continue;
         const DpClass c = class_of(*rest[q]);
@@ -1534,9 +1645,10 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
             hipError_t e = all && paired ? run_steps_paired<AT, CAP>(c, pack, s)
                                          : run_steps<AT, CAP>(c, pack, s);
             if (e != hipSuccess) return e;
+            if (all && paired) paired_jobs.insert(paired_jobs.end(), pack.begin(), pack.end());
         }
     }
-    return run_walks<AT, CAP>(jobs, s);
+    return run_walks<AT, CAP>(jobs, paired_jobs, s);
 }
 
 }  // namespace
