@@ -417,6 +417,24 @@ def main():
                                      **kw), max(3, args.steps // 5), stream), 4)
         del wsf
     line["dp_ms_by_bend_form"] = forms
+    # A through-point query (Sections 2.2-2.3): the whole detection with the
+    # polyline pinned at the middle band boundary, at the column the unpinned
+    # answer passes there.
+    if k >= 2:
+        pj = k // 2
+        pin = (pj, int(xs.cpu()[pj]))
+        opt = fhtp.make_options(0, False, pin)
+        wsp = torch.empty(fhtp.detect_ex_workspace_bytes(dt, h, w, k, bend, opt), dtype=torch.uint8,
+                          device=dev)
+        sc_p = torch.empty(1, dtype=torch.int32, device=dev)
+        xs_p = torch.empty(k + 1, dtype=torch.int32, device=dev)
+        line["through_point_ms"] = {
+            "pin": list(pin),
+            "detect_ms": round(time_events(
+                lambda: fhtp.detect_polyline_ex(img, k, bend=B, pin=pin, ws=wsp, score=sc_p, xs=xs_p,
+                                                stream=stream), max(3, args.steps // 5), stream), 4),
+        }
+        del wsp
     if args.batch_images > 0:
         line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream)
     if args.serve_requests > 0:

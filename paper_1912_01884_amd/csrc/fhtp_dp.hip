@@ -603,6 +603,11 @@ struct DpPairJob {
     int vin_pitch, h_pitch, v_pitch, a_pitch;
     int n, w, items_x, items_y;
     int item0;  // first workgroup of this image in the launch
+    // Through-point pin: on the cells read from vin (the table H_{k-1} read as
+    // V_{k-1}: 0 none, 1 x'' == pin, 2 x'' + d'' == pin), and on the cells of
+    // V_{i+1} (pin1_x) and V_i (pin0_x) made here (-1: none).
+    int vin_pin, vin_pin_x;
+    int pin1_x, pin0_x;
 };
 
 // CAP images per launch, as DpPack.
@@ -695,10 +700,14 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         const int xs = X0 + rs - (n - 1) + c;  // successor column x''
         const bool xs_ok = (unsigned)xs < (unsigned)w;
         // v[q] = V_{i+2}(x'', row rs - B + q): a cell when the row lies in
-        // [0, D) and x'' plus its displacement in [0, w)
+        // [0, D), x'' in [xlo, xlo + xlen) and x'' plus its displacement in
+        // [tlo, tlo + tlen) (both [0, w) unless vin carries a pin)
+        const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
         const int rlo = rs - B;
-        const int qlo = max(-rlo, (n - 1) - xs - rlo);
-        const int qhi = xs_ok ? min(D - rlo, (w + n - 1) - xs - rlo) : qlo;
+        const int qlo = max(-rlo, mk.tlo + (n - 1) - xs - rlo);
+        const int qhi = (unsigned)(xs - mk.xlo) < (unsigned)mk.xlen
+                            ? min(D - rlo, mk.tlo + mk.tlen + (n - 1) - xs - rlo)
+                            : qlo;
         // cell j exists when its row lies in [0, D), x' = X0 + c - j < w and
         // x'' lies in [0, w); it is in the tile when 0 <= c - j < 64
         const int jlo = max(-rs, X0 + c - w + 1);
@@ -708,7 +717,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         int* lrow = &mid[q0][LP + c];
         AT* nrow = &nxt[q0][LP + c];
         // A wave whose every load and cell is valid takes the unmasked copy.
-        const bool inner = qlo <= 0 && qhi >= NV1 && jlo <= 0 && jhi >= kStrip;
+        const bool inner = qlo <= 0 && qhi >= NV1 && jlo <= 0 && jhi >= kStrip && a.pin1_x < 0;
         auto strip = [&](auto inner_tag) {
             constexpr bool INNER = decltype(inner_tag)::value;
             int v[NV1];
@@ -733,7 +742,8 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
             window_max<B, kStrip>(v, m, ia);
 #pragma unroll
             for (int j = 0; j < kStrip; ++j) {
-                const bool live = INNER || (j >= jlo && j < jhi);
+                const bool live =
+                    INNER || (j >= jlo && j < jhi && (a.pin1_x < 0 || X0 + c - j == a.pin1_x));
                 const int val = live && m[j] >= 0 ? hv[j] + m[j] : -1;
                 lrow[j * (LWP - 1)] = val;
                 const int ra = rs - B + ia[j];  // row of the maximum's d''
@@ -768,7 +778,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     for (int j = 0; j < kPairDC; ++j) {
         const bool cell = j < jn;
         const bool live = cell && (unsigned)(xj - j) < (unsigned)w;
-        const int val = m2[j] >= 0 ? hv0[j] + m2[j] : -1;
+        const int val = m2[j] >= 0 && (a.pin0_x < 0 || xj - j == a.pin0_x) ? hv0[j] + m2[j] : -1;
         const int ra = r2 - B + ia2[j];
         const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
         const unsigned int av2 = nxt[wave * kPairDC + ia2[j]][LP + lane];  // the chosen cell's choice
@@ -1426,13 +1436,13 @@ hipError_t launch_pair(int bound, hipStream_t s, int grid, const DpPairPack<CAP>
 }
 
 // Two steps per launch need the fixed window, the 8-displacement chunk (an
-// image whose step grid leaves the chip latency-bound on its own), no pin,
-// and byte offsets inside a workgroup's rows that fit 32 bits.
+// image whose step grid leaves the chip latency-bound on its own) and byte
+// offsets inside a workgroup's rows that fit 32 bits.
 bool pairs_apply(const DpJobSpec& J) {
     const Geometry& g = J.g;
     const long long rows = kPairRows + 4LL * kMaxFixedB + kStrip;  // the widest view
     const long long pitch = std::max(g.W, g.pitch);
-    return J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC && J.pin.j < 0 && g.k >= 2 &&
+    return J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC && g.k >= 2 &&
            rows * pitch * 4 < 0x7fffffffLL;
 }
 
@@ -1479,6 +1489,8 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
             const int i = g.k - 2;  // its top band
             DpJob a = base_job(*J);
             input_of(*J, 0, a.vin, a.vin_pitch);
+            first_step_pin(*J, a.vin_pin, a.vin_pin_x);
+            a.out_pin_x = J->pin.j == i ? J->pin.x : -1;
             a.htab = J->tables + (size_t)i * ((size_t)g.D * g.W);
             a.vout = plane_of(*J, 0);
             a.aout = static_cast<AT*>(J->buf.a) + (size_t)(i - 1) * ((size_t)g.D * g.pitch);
@@ -1508,6 +1520,9 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
             AT* A = static_cast<AT*>(J->buf.a);
             DpPairJob a{};
             input_of(*J, odd + t, a.vin, a.vin_pitch);
+            if (odd + t == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);  // vin is H_{k-1}
+            a.pin1_x = J->pin.j == i ? J->pin.x : -1;
+            a.pin0_x = J->pin.j == i - 1 ? J->pin.x : -1;
             a.h1 = J->tables + (size_t)i * band;
             a.h0 = J->tables + (size_t)(i - 1) * band;
             a.vout = plane_of(*J, odd + t);
@@ -1539,6 +1554,8 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
         const int m = (P & 1) + P / 2;
         DpJob a = base_job(*J);
         input_of(*J, m, a.vin, a.vin_pitch);
+        if (m == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);  // k = 2: vin is H_1
+        a.out_pin_x = J->pin.j == 0 ? J->pin.x : -1;
         a.htab = J->tables;
         a.key = J->buf.key;
         a.succ = J->buf.succ;

@@ -66,6 +66,12 @@ PIN_CASES = [
     (128, 140, 4, np.uint16, dict(gamma=0.3)),        # angle windows
     (512, 300, 2, np.uint8, dict(bend=4)),            # n = 256: 16-bit back-pointers, 2 passes
     (1024, 1024, 16, np.uint8, dict(bend=4)),         # 1024^2 k=16 configuration shape
+    # two steps per launch with the pin inside a pair, on the table the first
+    # pair reads, on an odd top band stepped alone, and with 16-bit pointers
+    (80, 150, 5, np.uint8, dict(bend=3)),             # k = 5: top band alone, one pair
+    (144, 200, 9, np.uint16, dict(bend=8)),           # k = 9: top band alone, three pairs
+    (192, 110, 6, np.uint8, dict(bend=0)),            # k = 6: two pairs, straight lines
+    (1024, 120, 4, np.uint8, dict(bend=5)),           # n = 256, 16-bit back-pointers, one pair
 ]
 
 
