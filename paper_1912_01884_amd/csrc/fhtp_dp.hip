@@ -626,7 +626,9 @@ constexpr int kStripeTiles = 16;  // column tiles per stripe of the pair kernel'
 // row index and write nothing outside their rows.  All variable parts of an
 // offset go to the lane offset, which is what the hardware checks against
 // the view's extent.
-template <int B, typename AT, int CAP>
+// PIN: the through-point masks (a separate instantiation, so that unpinned
+// launches carry none of their instructions or registers).
+template <int B, typename AT, int CAP, bool PIN>
 __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP> pk) {
     constexpr int RM = kPairRows + 2 * B;  // rows of V_{i+1} the workgroup needs
     constexpr int NS = (RM + kStrip - 1) / kStrip;
@@ -702,7 +704,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         // v[q] = V_{i+2}(x'', row rs - B + q): a cell when the row lies in
         // [0, D), x'' in [xlo, xlo + xlen) and x'' plus its displacement in
         // [tlo, tlo + tlen) (both [0, w) unless vin carries a pin)
-        const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
+        const VMask mk = PIN ? vmask(w, a.vin_pin, a.vin_pin_x) : VMask{0, w, 0, w};
         const int rlo = rs - B;
         const int qlo = max(-rlo, mk.tlo + (n - 1) - xs - rlo);
         const int qhi = (unsigned)(xs - mk.xlo) < (unsigned)mk.xlen
@@ -717,7 +719,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         int* lrow = &mid[q0][LP + c];
         AT* nrow = &nxt[q0][LP + c];
         // A wave whose every load and cell is valid takes the unmasked copy.
-        const bool inner = qlo <= 0 && qhi >= NV1 && jlo <= 0 && jhi >= kStrip && a.pin1_x < 0;
+        const bool inner = qlo <= 0 && qhi >= NV1 && jlo <= 0 && jhi >= kStrip && (!PIN || a.pin1_x < 0);
         auto strip = [&](auto inner_tag) {
             constexpr bool INNER = decltype(inner_tag)::value;
             int v[NV1];
@@ -743,7 +745,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
 #pragma unroll
             for (int j = 0; j < kStrip; ++j) {
                 const bool live =
-                    INNER || (j >= jlo && j < jhi && (a.pin1_x < 0 || X0 + c - j == a.pin1_x));
+                    INNER || (j >= jlo && j < jhi && (!PIN || a.pin1_x < 0 || X0 + c - j == a.pin1_x));
                 const int val = live && m[j] >= 0 ? hv[j] + m[j] : -1;
                 lrow[j * (LWP - 1)] = val;
                 const int ra = rs - B + ia[j];  // row of the maximum's d''
@@ -778,7 +780,8 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     for (int j = 0; j < kPairDC; ++j) {
         const bool cell = j < jn;
         const bool live = cell && (unsigned)(xj - j) < (unsigned)w;
-        const int val = m2[j] >= 0 && (a.pin0_x < 0 || xj - j == a.pin0_x) ? hv0[j] + m2[j] : -1;
+        const int val =
+            m2[j] >= 0 && (!PIN || a.pin0_x < 0 || xj - j == a.pin0_x) ? hv0[j] + m2[j] : -1;
         const int ra = r2 - B + ia2[j];
         const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
         const unsigned int av2 = nxt[wave * kPairDC + ia2[j]][LP + lane];  // the chosen cell's choice
@@ -1420,12 +1423,12 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
     return hipSuccess;
 }
 
-template <typename AT, int CAP>
-hipError_t launch_pair(int bound, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
-#define FHTP_B(BB)                                                                          \
-    case BB:                                                                                \
-        hipLaunchKernelGGL((dp_pair_fixed<BB, AT, CAP>), dim3(grid), dim3(64 * kPairWaves), 0, \
-                           s, pk);                                                          \
+template <typename AT, int CAP, bool PIN>
+hipError_t launch_pair_p(int bound, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
+#define FHTP_B(BB)                                                                               \
+    case BB:                                                                                     \
+        hipLaunchKernelGGL((dp_pair_fixed<BB, AT, CAP, PIN>), dim3(grid), dim3(64 * kPairWaves), \
+                           0, s, pk);                                                            \
         return hipSuccess;
     switch (bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
@@ -1433,6 +1436,17 @@ hipError_t launch_pair(int bound, hipStream_t s, int grid, const DpPairPack<CAP>
         default: return hipErrorInvalidValue;
     }
 #undef FHTP_B
+}
+
+// Pinned packs exist only for single images (a batch job has no pin).
+template <typename AT, int CAP>
+hipError_t launch_pair(int bound, bool pinned, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
+    if constexpr (CAP == 1) {
+        if (pinned) return launch_pair_p<AT, CAP, true>(bound, s, grid, pk);
+    } else {
+        if (pinned) return hipErrorInvalidValue;
+    }
+    return launch_pair_p<AT, CAP, false>(bound, s, grid, pk);
 }
 
 // Two steps per launch need the fixed window, the 8-displacement chunk (an
@@ -1541,7 +1555,10 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
             pk.job[cnt++] = a;
         }
         pk.count = cnt;
-        hipError_t e = launch_pair<AT, CAP>(jobs[0]->plan.bound, s, (int)total, pk);
+        bool pinned = false;
+        for (int q = 0; q < cnt; ++q)
+            pinned = pinned || pk.job[q].vin_pin != 0 || pk.job[q].pin1_x >= 0 || pk.job[q].pin0_x >= 0;
+        hipError_t e = launch_pair<AT, CAP>(jobs[0]->plan.bound, pinned, s, (int)total, pk);
         if (e != hipSuccess) return e;
     }
     // last step of every image: V_1 (or the table H_1 when k = 2) to the keys
@@ -1656,7 +1673,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
             bool paired = false;  // every image qualifies and one has a pair of steps
             bool all = true;
             for (const DpJobSpec* J : pack) {
-                all = all && pairs_apply(*J);
+                all = all && pairs_apply(*J) && (CAP == 1 || J->pin.j < 0);
                 paired = paired || J->g.k >= 4;
             }
             hipError_t e = all && paired ? run_steps_paired<AT, CAP>(c, pack, s)
