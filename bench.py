@@ -25,26 +25,34 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 
-# HBM bytes per launch of the band FHT kernel on the 4096x4096 uint16 image
-# (k = 32), from two rocprofv3 --pmc runs of `bench.py --probe` (FETCH_SIZE,
-# then WRITE_SIZE), each scaled by what the same counter reads for a copy of a
-# known size in the same run.  Valid only for the kernel source they were
-# taken on (sha256 of csrc/fhtp_fht.hip); otherwise the traffic is unknown.
-FHT_TRAFFIC = {"source_sha256": "7b1ac4b7416bda6e4842dd87714b9d40e083681e4821b0d889f36885ddba7dc4",
-               "fetch_bytes": 46875988, "write_bytes": 151035200}
+# HBM bytes per launch of each kernel family on the 4096x4096 uint16 image
+# (k = 32, bend 8), from two rocprofv3 --pmc runs of `bench.py --probe`
+# (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads
+# for a copy of a known size in the same run (`bench.py --summarize-counters`).
+# Valid only for the kernel source they were taken on (sha256 of the file);
+# otherwise the traffic is unknown and reported as null.
+TRAFFIC = {}
 
 
 def byte_model(h, w, k, bpp):
-    """Algorithmic HBM bytes of one detection with materialised band tables."""
+    """Algorithmic HBM bytes of one detection with materialised band tables.
+
+    The image is read once, the tables [k][2n-1][w+n] int32 are written once
+    by the FHT and read once by the DP, and one back-pointer per DP cell and
+    band boundary is written ((k-1)(2n-1)w of them, one byte each while 2n-1
+    fits a byte, else two).  The DP's value planes are not counted: the
+    dataflow keeps them in cache, and their traffic is reported apart.
+    """
     n = h // k
     D, W = 2 * n - 1, w + n
+    ab = 1 if D <= 256 else 2
     image = h * w * bpp
     tables = 4 * k * D * W
-    # back-pointer planes for bands 2..k-1 (the first successor is recorded by
-    # the last step with its keys)
-    backptr = max(k - 2, 0) * D * w * (1 if D <= 256 else 2)
+    backptr = max(k - 1, 0) * D * w * ab
     return {"image": image, "tables_write": tables, "tables_read": tables, "backptr": backptr,
-            "total": image + 2 * tables + backptr, "fht_kernel": image + tables}
+            "total": image + 2 * tables + backptr, "fht_kernel": image + tables,
+            "dp_per_band": 4 * D * W + D * w * ab, "table_read_per_band": 4 * D * W,
+            "backptr_per_band": D * w * ab, "v_plane": 4 * D * w}
 
 
 def time_events(fn, reps, stream):
@@ -60,19 +68,55 @@ def time_events(fn, reps, stream):
 
 
 def cpu_baseline(img, k, bend, seconds):
+    """The oracle on all host cores, repeated on the same image for about
+    `seconds`; returns the baseline entry and the oracle's answer."""
     import oracle
     h, w = img.shape
     runs = 0
     t0 = time.perf_counter()
     while True:
-        oracle.detect_polyline(img, k, bend=bend)
+        res = oracle.detect_polyline(img, k, bend=bend)
         runs += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return {"value": round(h * w * runs / el / 1e6, 3), "unit": "Mpix/s",
-            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
-            "sample": f"{runs} full detection(s) of the {h}x{w} image, {el:.1f} s"}
+    return ({"value": round(h * w * runs / el / 1e6, 3), "unit": "Mpix/s",
+             "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
+             "sample": f"{runs} full detection(s) of the {h}x{w} image, {el:.1f} s"},
+            (int(res[0]), [int(v) for v in res[1]]))
+
+
+SINGLE_THREAD_SNIPPET = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle, synth
+out = {}
+for name, secs in (("64x64", float(sys.argv[2])), ("1024x1024", float(sys.argv[2]))):
+    s = synth.make_config(name)
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        oracle.detect_polyline(s.image, s.k, bend=s.bend)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= secs:
+            break
+    out[name] = {"value": round(s.h * s.w * runs / el / 1e6, 3), "unit": "Mpix/s",
+                 "ms_per_detection": round(el / runs * 1e3, 3), "cores": oracle.num_threads(),
+                 "sample": f"{runs} detection(s), {el:.1f} s"}
+print(json.dumps(out))
+"""
+
+
+def cpu_single_thread(seconds):
+    """The oracle on one host core (OMP_NUM_THREADS=1, a child process) on the
+    64x64 and 1024x1024 workloads."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", SINGLE_THREAD_SNIPPET, ROOT, str(seconds)],
+                       capture_output=True, text=True, env=env, timeout=120)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def cpu_model():
@@ -150,13 +194,31 @@ def mixed_batch(n_images, reps, dev, stream):
     torch.cuda.synchronize()
     ms_plain = time_events(plain, reps, stream)
     ms_batch = time_events(batched, reps, stream)
+    first = [(int(sc.cpu()[0]), x.cpu().tolist()) for sc, x in keep]
+
+    # The steady state: the same batch recorded once as a HIP graph
+    # (fhtp_plan_create / _capture) and replayed with fhtp_plan_launch.
+    plan = fhtp.Plan(imgs, [s.k for s in batch], bends=[s.bend for s in batch],
+                     scores=[sc for sc, _ in keep], xss=[x for _, x in keep], ws=wsb)
+    for sc, x in keep:
+        sc.fill_(-1)
+        x.fill_(-1)
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    same = [(int(sc.cpu()[0]), x.cpu().tolist()) for sc, x in keep] == first
+    ms_graph = time_events(lambda: plan.launch(stream), reps, stream)
+    plan.destroy()
     mpix = sum(s.h * s.w for s in batch) / 1e6
+    best = min(ms_batch, ms_graph)
     return {"images": n_images, "mpix_per_batch": round(mpix, 2),
             "plain_images_per_s": round(n_images / (ms_plain * 1e-3), 1),
             "batched_images_per_s": round(n_images / (ms_batch * 1e-3), 1),
+            "graph_images_per_s": round(n_images / (ms_graph * 1e-3), 1),
             "plain_ms": round(ms_plain, 3), "batched_ms": round(ms_batch, 3),
+            "graph_ms": round(ms_graph, 3), "graph_identical_to_batched": same,
             "speedup": round(ms_plain / ms_batch, 2),
-            "batched_mpix_per_s": round(mpix / (ms_batch * 1e-3), 1)}
+            "graph_speedup": round(ms_plain / ms_graph, 2),
+            "batched_mpix_per_s": round(mpix / (best * 1e-3), 1)}
 
 
 def serving(dev, rates, count, streams=4, max_batch=256):
@@ -214,19 +276,88 @@ def serving(dev, rates, count, streams=4, max_batch=256):
     return res
 
 
-def fht_traffic():
+
+
+def source_sha(rel):
     import hashlib
-    if FHT_TRAFFIC is None:
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_of(family):
+    """Counter bytes (fetched + written) per launch of a kernel family on the
+    4096x4096 workload, or None when not taken on the current source."""
+    t = TRAFFIC.get(family)
+    if not t or source_sha(t["source"]) != t["source_sha256"]:
         return None
-    src = os.path.join(ROOT, "paper_1912_01884_amd", "csrc", "fhtp_fht.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != FHT_TRAFFIC["source_sha256"]:
+    return t["fetch_bytes"] + t["write_bytes"]
+
+
+def kernel_alg_bytes(family, model, launches):
+    """Algorithmic bytes of one launch of a kernel family in one detection
+    (the byte model's per-unit figures times the units one launch handles)."""
+    if family == "fht_reg_kernel" and launches == 1:
+        return model["fht_kernel"]  # the image read, every band's table written
+    per_band = model["dp_per_band"]  # a band's table read, its back-pointers written
+    bands = {"dp_pair_fixed": 2, "dp_triple_fixed": 3, "dp_step_fixed": 1,
+             "dp_step_generic": 1}.get(family)
+    return None if bands is None else bands * per_band
+
+
+def kernel_breakdown(step, reps):
+    """Per-kernel launch times of `reps` detections, from the library's event
+    brackets (fhtp_timing_start / _stop) on the launch stream."""
+    import torch
+    from paper_1912_01884_amd import fhtp
+    torch.cuda.synchronize()
+    fhtp.timing_start()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    fam = fhtp.timing_stop()
+    return {name: {"launches_per_detection": round(n / reps, 3),
+                   "avg_launch_us": round(ms * 1e3 / n, 3),
+                   "us_per_detection": round(ms * 1e3 / reps, 3)}
+            for name, (n, ms) in fam.items()}
+
+
+def roofline_of(family, info, model):
+    per = info["launches_per_detection"]
+    alg = kernel_alg_bytes(family, model, per)
+    if alg is None:
         return None
-    return FHT_TRAFFIC["fetch_bytes"] + FHT_TRAFFIC["write_bytes"]
+    t = info["avg_launch_us"] * 1e-6
+    gbps = alg / t / 1e9
+    out = {"bound": "hbm", "kernel": family, "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+           "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_of(family),
+           "algorithmic_bytes": alg, "avg_launch_us": info["avg_launch_us"],
+           "launches_per_detection": per}
+    if out["traffic"] is not None:
+        tg = out["traffic"] / t / 1e9
+        out["achieved_traffic"] = round(tg, 1)
+        out["traffic_frac"] = round(tg / HBM_PEAK_GBPS, 4)
+        out["traffic_over_algorithmic"] = round(out["traffic"] / alg, 3)
+    return out
+
+
+def copy_bandwidth(dev, stream, reps=10):
+    """Attainable HBM bandwidth: a 1 GiB device-to-device copy timed with events
+    (bytes read + bytes written per second)."""
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ms = time_events(lambda: b.copy_(a), reps, stream)
+    del a, b
+    return {"bytes": 2 << 30, "gbps": round((2 << 30) / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round((2 << 30) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
 def probe(dev):
     """A short program for hardware-counter runs: a 256 MiB fill and copy of known
-    size (counter calibration), then one band FHT and one DP of the 4096x4096 image."""
+    size (counter calibration), then one whole detection of the 4096x4096 image."""
     import torch
 
     import synth
@@ -239,11 +370,105 @@ def probe(dev):
     torch.cuda.synchronize()
     a.fill_(1)
     b.copy_(a)
-    tables = fhtp.fht_bands(img, s.k)
-    score, xs = fhtp.polyline_dp(tables, s.h, s.w, s.k, bend=s.bend)
+    score, xs = fhtp.detect_polyline(img, s.k, bend=s.bend)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "copy 268435456 bytes; fht_bands + polyline_dp 4096x4096 k=32",
+    print(json.dumps({"probe": "fill + copy 268435456 bytes; detect_polyline 4096x4096 k=32",
                       "score": int(score.cpu()[0])}), flush=True)
+
+
+# ---- rocprofv3 output summaries ------------------------------------------------
+
+def _csv_rows(folder, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(folder, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {folder}")
+    return rows
+
+
+def _short(name, width=90):
+    name = name.replace("void ", "").replace("fhtp::(anonymous namespace)::", "")
+    return name if len(name) <= width else name[:width - 3] + "..."
+
+
+def summarize_trace(folder):
+    """Markdown table of a `rocprofv3 --kernel-trace --stats` run: per kernel
+    calls and durations, then the kernels of the last whole detection."""
+    rows = _csv_rows(folder, "kernel_trace.csv")
+    by = {}
+    seq = []
+    for r in rows:
+        name = _short(r["Kernel_Name"])
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        by.setdefault(name, []).append(us)
+        seq.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), name, us))
+    total = sum(sum(v) for v in by.values())
+    print("| kernel | calls | avg us | median us | min us | max us | share |")
+    print("|---|---|---|---|---|---|---|")
+    for name, v in sorted(by.items(), key=lambda kv: -sum(kv[1]))[:14]:
+        v = sorted(v)
+        print(f"| `{name}` | {len(v)} | {sum(v) / len(v):.2f} | {v[len(v) // 2]:.2f} | "
+              f"{v[0]:.2f} | {v[-1]:.2f} | {100 * sum(v) / total:.1f}% |")
+    seq.sort()
+    starts = [q for q, e in enumerate(seq) if e[2].startswith("fht_reg_kernel")]
+    for q0 in reversed(starts):
+        q1 = next((q for q in range(q0, len(seq)) if seq[q][2].startswith("walk")), None)
+        if q1 is None:
+            continue
+        print("\nOne detection (the last one traced; kernels in launch order):\n")
+        run = {}
+        order = []
+        for e in seq[q0:q1 + 1]:
+            if e[2] not in run:
+                order.append(e[2])
+            run.setdefault(e[2], []).append(e[3])
+        for name in order:
+            v = run[name]
+            if len(v) == 1:
+                print(f"- `{name}`: {v[0]:.2f}")
+            else:
+                print(f"- `{name}` x{len(v)}: total {sum(v):.1f}, mean {sum(v) / len(v):.2f}, "
+                      f"min {min(v):.2f}, max {max(v):.2f}")
+        print(f"- first kernel start to walk end: {(seq[q1][1] - seq[q0][0]) / 1e3:.1f}")
+        break
+
+
+def summarize_counters(fetch_dir, write_dir):
+    """Markdown table of two `rocprofv3 --pmc` runs of `bench.py --probe`
+    (FETCH_SIZE, then WRITE_SIZE): the counters per dispatch, scaled by what
+    they read for the probe's 256 MiB copy (FETCH_SIZE) and fill (WRITE_SIZE)."""
+    mib256 = 256 * 1024  # KiB
+
+    def per_kernel(folder, counter):
+        out = {}
+        for r in _csv_rows(folder, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(_short(r["Kernel_Name"], 200), []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    copy_f = next(v for k, v in fetch.items() if "copyBuffer" in k or "copy" in k.lower())
+    fill_w = next(v for k, v in write.items() if "Fill" in k or "fill" in k)
+    sf = copy_f[-1] / mib256
+    sw = fill_w[-1] / mib256
+    print(f"Calibration: FETCH_SIZE reads {sf:.4f} x the bytes the copy fetched, "
+          f"WRITE_SIZE {sw:.4f} x the bytes the fill wrote.\n")
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetched (scaled) | "
+          "written (scaled) |")
+    print("|---|---|---|---|---|---|")
+    for name in fetch:
+        if name not in write:
+            continue
+        f, w = fetch[name], write[name]
+        mf, mw = sum(f) / len(f), sum(w) / len(w)
+        print(f"| `{_short(name)}` | {len(f)} | {mf:.1f} | {mw:.1f} | "
+              f"{mf / sf * 1024 / 1e6:.2f} MB | {mw / sw * 1024 / 1e6:.2f} MB |")
 
 
 def main():
@@ -263,15 +488,24 @@ def main():
                     help="Poisson arrival rates (requests/s) of the serving run; inf = all at once")
     ap.add_argument("--probe", action="store_true",
                     help="run the short counter-calibration program instead of the benchmark")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print the kernel table of a rocprofv3 --kernel-trace run and exit")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic table of two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
 
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
               "(independent images and requests would shard one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import synth
@@ -303,6 +537,7 @@ def main():
     ms_eager = time_events(step, args.steps, stream)
     torch.cuda.synchronize()
     wall_eager = time.perf_counter() - t0
+    result = (int(score.cpu()[0]), xs.cpu().numpy().tolist())
 
     # The same detection recorded once as a HIP graph by the library's plan
     # calls (fhtp_plan_create / _capture) and replayed with fhtp_plan_launch:
@@ -319,12 +554,17 @@ def main():
     ms_graph = time_events(replay, args.steps, stream)
     torch.cuda.synchronize()
     wall_graph = time.perf_counter() - t0
+    graph_result = (int(score.cpu()[0]), xs.cpu().numpy().tolist())
     # Both are full timed runs of the same detection; the step time is the
     # faster of the two submission paths (graph replays carry a fixed host
     # cost per launch that can exceed the GPU time of one detection).
     ms_per_step = max(min(ms_graph, ms_eager), 1e-9)
     launch = ("fhtp_plan_launch: hip graph replay of one detection" if ms_graph <= ms_eager
               else "fhtp_detect_polyline: one call per detection, kernels launched on the stream")
+
+    # Per-kernel launch times of the same detection (event brackets on the
+    # launch stream, outside the timed region above).
+    kernels = kernel_breakdown(step, max(5, args.steps // 2))
 
     # Single detections timed one by one: warm (tables and planes of the
     # previous detection still in L2/MALL) and cold (a 1 GiB buffer written
@@ -333,8 +573,9 @@ def main():
     flush_buf = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     single_cold = single_detections(step, stream, 10, flush=lambda: flush_buf.fill_(1))
     del flush_buf
+    copy_bw = copy_bandwidth(dev, stream)
 
-    # Phase timings on the same stream: the band FHT (one kernel) and the DP.
+    # Phase timings on the same stream: the band FHT and the DP.
     tables = torch.empty(fhtp.table_shape(h, w, k), dtype=torch.int32, device=dev)
     fws_n = fhtp.fht_workspace_bytes(dt, h, w, k)
     fws = torch.empty(max(fws_n, 1), dtype=torch.uint8, device=dev)
@@ -345,32 +586,27 @@ def main():
                                                  xs=xs, stream=stream), args.steps, stream)
 
     model = byte_model(h, w, k, bpp)
-    fht_gbps = model["fht_kernel"] / (ms_fht * 1e-3) / 1e9
-    # Algorithmic bytes of the DP phase (columns < w, 4 bytes a value cell,
-    # 1 or 2 bytes a back-pointer).  A single image with a fixed window of at
-    # most 16 shifts on a grid that leaves the chip latency-bound (fewer than
-    # 2^17 threads at 16 displacements each) takes bands k-2..1 two per launch
-    # (reads V_{i+2}, H_{i+1}, H_i; writes V_i, A_{i+2}, A_{i+1}), one single
-    # step first when their count is odd (reads H_i, V_{i+1}; writes V_i,
-    # A_{i+1}); the last step reads H_0 and V_1 and writes keys.  The phase
-    # time includes the backtrace walk, so the figure is a lower bound.
-    D = 2 * (h // k) - 1
-    ab = 1 if D <= 256 else 2
-    cells = D * w
-    paired = B <= 16 and k >= 4 and w * ((D + 15) // 16) < 1 << 17
-    bands = max(k - 2, 0)
-    pairs, singles = (bands // 2, bands % 2) if paired else (0, bands)
-    dp_bytes = cells * (pairs * (16 + 2 * ab) + singles * (12 + ab) + (8 if k >= 2 else 4))
-    launches = pairs + singles + 1
+    # The kernel with the most time per detection carries the roofline object.
+    roofs = {f: roofline_of(f, info, model) for f, info in kernels.items()}
+    ranked = sorted((f for f in roofs if roofs[f] is not None),
+                    key=lambda f: -kernels[f]["us_per_detection"])
+    dominant = ranked[0] if ranked else None
+
+    def whole(ms):
+        g = model["total"] / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": "whole detection", "achieved": round(g, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(g / HBM_PEAK_GBPS, 4),
+                "ms": round(ms, 4), "algorithmic_bytes": model["total"]}
+
+    # DP phase: the tables it reads and the back-pointers it writes (the byte
+    # model's DP share); the value planes it passes between launches are
+    # reported apart (each launch reads one plane and writes one).
+    dp_launches = sum(v["launches_per_detection"] for f, v in kernels.items()
+                      if f.startswith("dp_"))
+    dp_bytes = model["tables_read"] + model["backptr"]
     dp_gbps = dp_bytes / (ms_dp * 1e-3) / 1e9
-    dp_roofline = {"bound": "hbm",
-                   "kernel": f"dp_pair_fixed x{pairs} + dp_step_fixed x{singles + 1} + walk",
-                   "achieved": round(dp_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                   "frac": round(dp_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
-                   "algorithmic_bytes": dp_bytes, "launches": launches,
-                   "us_per_launch_incl_walk": round(ms_dp * 1e3 / launches, 3)}
     line = {
-        "metric": "FHT+DP Mpix/s & HBM GB/s @4096\u00b2,k=32; batched imgs/s vs plain; p99 ms",
+        "metric": "FHT+DP Mpix/s & HBM GB/s @4096²,k=32; batched imgs/s vs plain; p99 ms",
         "value": round(h * w / (ms_per_step * 1e-3) / 1e6, 2),
         "unit": "Mpix/s",
         "n_gpus": 1,
@@ -389,18 +625,24 @@ def main():
                    "h": h, "w": w, "k": k, "bend": B, "pixel": s.image.dtype.name},
         "images_per_s": round(1e3 / ms_per_step, 2),
         "hbm_gbps_model": round(model["total"] / (ms_per_step * 1e-3) / 1e9, 1),
-        "model_bytes": model,
+        "model_bytes": {q: model[q] for q in ("image", "tables_write", "tables_read", "backptr",
+                                              "total")},
         "launch": launch,
         "eager_ms_per_step": round(ms_eager, 4),
         "graph_ms_per_step": round(ms_graph, 4),
         "phase_ms": {"fht_bands": round(ms_fht, 4), "polyline_dp": round(ms_dp, 4)},
+        "kernels": kernels,
         "single_detection_ms": {"warm": single_warm, "cold": single_cold},
-        "roofline": {"bound": "hbm", "kernel": "fht_reg_kernel",
-                     "achieved": round(fht_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(fht_gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": fht_traffic() if (h, w, k, bpp) == (4096, 4096, 32, 2) else None,
-                     "algorithmic_bytes": model["fht_kernel"]},
-        "roofline_dp_phase": dp_roofline,
+        "roofline": roofs.get(dominant),
+        "roofline_fht": roofs.get("fht_reg_kernel"),
+        "roofline_detection": {"warm": whole(ms_per_step), "cold": whole(single_cold["median"])},
+        "roofline_dp_phase": {"bound": "hbm", "kernel": "every DP launch + walk",
+                              "achieved": round(dp_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                              "frac": round(dp_gbps / HBM_PEAK_GBPS, 4),
+                              "algorithmic_bytes": dp_bytes, "ms": round(ms_dp, 4),
+                              "dp_launches": round(dp_launches, 3),
+                              "v_plane_bytes_per_launch": 2 * model["v_plane"]},
+        "copy_bandwidth": copy_bw,
     }
     # The DP under the other bend forms on the same tables: the angle bound of
     # eqs. (6)-(7) and the unbounded case of Section 2.2 (scanned windows).
@@ -422,7 +664,7 @@ def main():
     # answer passes there.
     if k >= 2:
         pj = k // 2
-        pin = (pj, int(xs.cpu()[pj]))
+        pin = (pj, int(result[1][pj]))
         opt = fhtp.make_options(0, False, pin)
         wsp = torch.empty(fhtp.detect_ex_workspace_bytes(dt, h, w, k, bend, opt), dtype=torch.uint8,
                           device=dev)
@@ -444,10 +686,20 @@ def main():
         if k1000:
             line["p99_ms"] = k1000["server"]["p99_ms"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(s.image, k, B, args.cpu_seconds)
-    res = (int(score.cpu()[0]), xs.cpu().numpy().tolist())
-    line["result"] = {"score": res[0], "x0": res[1][0], "xk": res[1][-1]}
+        base, want = cpu_baseline(s.image, k, B, args.cpu_seconds)
+        base["single_thread"] = cpu_single_thread(3.0)
+        line["cpu_baseline"] = base
+    else:
+        import oracle
+        want = oracle.detect_polyline(s.image, k, bend=B)
+        want = (int(want[0]), [int(v) for v in want[1]])
+    # The timed detection's answer (eager calls and graph replays) against the oracle.
+    line["parity"] = bool(result == want and graph_result == want)
+    line["result"] = {"score": result[0], "x0": result[1][0], "xk": result[1][-1]}
     print(json.dumps(line), flush=True)
+    if not line["parity"]:
+        print(f"parity failure: gpu {result} / {graph_result}, oracle {want}", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

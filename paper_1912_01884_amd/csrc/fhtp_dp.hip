@@ -1334,6 +1334,7 @@ int items_y_of(const Geometry& g, int dc) {
 
 template <int B, typename AT, int CAP>
 void launch_fixed_b(int dc, hipStream_t s, const DpPack<CAP>& pk) {
+    TimedLaunch tl("dp_step_fixed", s);
     if (dc == 8)
         hipLaunchKernelGGL((dp_step_fixed<B, 8, AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
     else
@@ -1343,6 +1344,7 @@ void launch_fixed_b(int dc, hipStream_t s, const DpPack<CAP>& pk) {
 template <typename AT, int CAP>
 hipError_t launch_step(const DpClass& c, hipStream_t s, const DpPack<CAP>& pk) {
     if (c.kind != (int)WindowKind::Fixed) {
+        TimedLaunch tl("dp_step_generic", s);
         hipLaunchKernelGGL((dp_step_generic<AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
         return hipSuccess;
     }
@@ -1426,10 +1428,12 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
 template <typename AT, int CAP, bool PIN>
 hipError_t launch_pair_p(int bound, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
 #define FHTP_B(BB)                                                                               \
-    case BB:                                                                                     \
+    case BB: {                                                                                   \
+        TimedLaunch tl("dp_pair_fixed", s);                                                      \
         hipLaunchKernelGGL((dp_pair_fixed<BB, AT, CAP, PIN>), dim3(grid), dim3(64 * kPairWaves), \
                            0, s, pk);                                                            \
-        return hipSuccess;
+        return hipSuccess;                                                                       \
+    }
     switch (bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
         FHTP_B(9) FHTP_B(10) FHTP_B(11) FHTP_B(12) FHTP_B(13) FHTP_B(14) FHTP_B(15) FHTP_B(16)
@@ -1618,7 +1622,10 @@ hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs,
             a.pair_top = in_pairs ? (g.k - 2) - ((g.k - 2) & 1) : 0;
         }
         pk.count = cnt;
-        hipLaunchKernelGGL((walk<AT, CAP>), dim3(cnt), dim3(64), 0, s, pk);
+        {
+            TimedLaunch tl("walk", s);
+            hipLaunchKernelGGL((walk<AT, CAP>), dim3(cnt), dim3(64), 0, s, pk);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1650,6 +1657,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
         }
         pk.count = cnt;
         pk.total = (int)total;
+        TimedLaunch tl("argmax_table", s);
         hipLaunchKernelGGL((argmax_table<CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
     }
     // k >= 2: step launches per class, in packs.
@@ -1707,9 +1715,11 @@ hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t s) {
         if (J.plan.kind == WindowKind::Fixed &&
             (J.plan.bound < 0 || J.plan.bound > kMaxFixedB || (J.plan.dc != 8 && J.plan.dc != 16)))
             return hipErrorInvalidValue;
-        if (J.plan.kind == WindowKind::Angle)
+        if (J.plan.kind == WindowKind::Angle) {
+            TimedLaunch tl("angle_windows", s);
             hipLaunchKernelGGL(angle_windows, dim3((J.g.D + 255) / 256), dim3(256), 0, s, J.g.n,
                                J.plan.tan_gamma, J.buf.win);
+        }
         (J.plan.a16 ? a16 : a8).push_back(&J);
     }
     hipError_t e = hipSuccess;

@@ -569,7 +569,10 @@ hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
     if (total == 0) return hipSuccess;
     const long long slots = (long long)occupancy * device_cus();
     const int grid = (int)(total < slots ? total : slots);
-    hipLaunchKernelGGL((fht_reg_kernel<P, PixT, CAP>), dim3(grid), dim3(C::NT), 0, stream, pk);
+    {
+        TimedLaunch tl("fht_reg_kernel", stream);
+        hipLaunchKernelGGL((fht_reg_kernel<P, PixT, CAP>), dim3(grid), dim3(C::NT), 0, stream, pk);
+    }
     return hipGetLastError();
 }
 
@@ -672,6 +675,7 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
             }
             pk.count = n;
             pk.total = (int)total;
+            TimedLaunch tl("fht_combine_kernel", stream);
             if (sh == 1)
                 hipLaunchKernelGGL(fht_combine_kernel<1>, dim3((unsigned)total), dim3(256), 0, stream, pk);
             else if (sh == 2)

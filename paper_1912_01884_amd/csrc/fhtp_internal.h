@@ -18,6 +18,22 @@ struct Geometry {
     int pitch;  // row pitch (elements) of the DP planes: w rounded up to 64
 };
 
+// Brackets one kernel launch with events while benchmark timing is on
+// (fhtp_timing_start); a no-op otherwise.  Construct it right before the
+// launch, on the launch's stream; the bracket closes when it goes out of scope.
+class TimedLaunch {
+public:
+    TimedLaunch(const char* family, hipStream_t s);
+    ~TimedLaunch();
+    TimedLaunch(const TimedLaunch&) = delete;
+    TimedLaunch& operator=(const TimedLaunch&) = delete;
+
+private:
+    const char* family_;
+    hipStream_t stream_;
+    hipEvent_t begin_ = nullptr;
+};
+
 // Largest band height the register FHT kernel handles in one pass.
 constexpr int kRegMaxP = 7;
 

@@ -95,6 +95,7 @@ hipError_t launch_prep(const void* img, int dtype, int h, int w, int radius, int
     for (int i = 1; i <= 2 * radius; ++i) a.coef[i] = a.coef[i - 1] * (2 * radius - i + 1) / i;
     const int tiles_y = (a.ho + kTile - 1) / kTile;
     const dim3 grid((a.wo + kTile - 1) / kTile, tiles_y < 65535 ? tiles_y : 65535);
+    TimedLaunch tl("prep_kernel", stream);
     if (dtype == 0)
         hipLaunchKernelGGL(prep_kernel<uint8_t>, grid, dim3(kThreads), 0, stream, a);
     else

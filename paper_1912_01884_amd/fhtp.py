@@ -36,7 +36,7 @@ EXPORTED = (
     "fhtp_detect_workspace_bytes", "fhtp_detect_polyline", "fhtp_batch_workspace_bytes",
     "fhtp_detect_batch", "fhtp_detect_ex_workspace_bytes", "fhtp_detect_polyline_ex",
     "fhtp_prepare_image", "fhtp_plan_create", "fhtp_plan_capture", "fhtp_plan_launch",
-    "fhtp_plan_destroy",
+    "fhtp_plan_destroy", "fhtp_timing_start", "fhtp_timing_stop",
 )
 
 
@@ -60,6 +60,12 @@ class Job(C.Structure):
 
     _fields_ = [("img", C.c_void_p), ("dtype", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
                 ("k", C.c_int32), ("bend", Bend), ("score", C.c_void_p), ("xs", C.c_void_p)]
+
+
+class KernelTime(C.Structure):
+    """fhtp_kernel_time: one kernel family's launches and summed bracket time."""
+
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int32), ("total_ms", C.c_double)]
 
 
 class Options(C.Structure):
@@ -118,6 +124,8 @@ def lib() -> C.CDLL:
     L.fhtp_plan_capture.argtypes = [vp]
     L.fhtp_plan_launch.argtypes = [vp, vp]
     L.fhtp_plan_destroy.argtypes = [vp]
+    L.fhtp_timing_start.argtypes = []
+    L.fhtp_timing_stop.argtypes = [C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
     for name in EXPORTED:
         if name not in ("fhtp_strerror", "fhtp_last_error_detail", "fhtp_version"):
             getattr(L, name).restype = C.c_int
@@ -176,6 +184,21 @@ def detect_ex_workspace_bytes(dtype: int, h: int, w: int, k: int, bend: Bend,
     return out.value
 
 
+def timing_start() -> None:
+    """Bracket every following library launch with events (benchmarks only)."""
+    _check(lib().fhtp_timing_start(), "timing_start")
+
+
+def timing_stop() -> dict:
+    """Stop timing; {family: (launches, total_ms)} in order of first launch."""
+    cap = 64
+    arr = (KernelTime * cap)()
+    cnt = C.c_int()
+    _check(lib().fhtp_timing_stop(arr, cap, C.byref(cnt)), "timing_stop")
+    return {arr[q].name.decode(): (int(arr[q].launches), float(arr[q].total_ms))
+            for q in range(min(cnt.value, cap))}
+
+
 # ---- torch marshalling ------------------------------------------------------
 
 def _torch():
@@ -196,6 +219,21 @@ def _stream_ptr(stream) -> int:
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
+
+
+def _on_stream(stream):
+    """Context in which temporaries are allocated: the launch stream.
+
+    torch's caching allocator hands a freed block only to later allocations
+    on the stream it was allocated on, so a workspace or output allocated here
+    and dropped after the call cannot be reused while the kernels enqueued on
+    `stream` still use it, whichever stream is current.
+    """
+    import contextlib
+    torch = _torch()
+    if stream is None:
+        return contextlib.nullcontext()
+    return torch.cuda.stream(stream)
 
 
 def _require_device(t, name: str):
@@ -223,11 +261,12 @@ def fht_bands(img, k: int, tables=None, ws=None, stream=None):
     h, w = img.shape
     dt = _dtype_code(img)
     kk, D, W = table_shape(h, w, k)
-    if tables is None:
-        tables = torch.empty((kk, D, W), dtype=torch.int32, device=img.device)
-    ws_t, ws_n = _ws(fht_workspace_bytes(dt, h, w, k), img.device, ws)
-    rc = lib().fhtp_fht_bands(img.data_ptr(), dt, h, w, k, tables.data_ptr(), _ptr(ws_t), ws_n,
-                              _stream_ptr(stream))
+    with _on_stream(stream):
+        if tables is None:
+            tables = torch.empty((kk, D, W), dtype=torch.int32, device=img.device)
+        ws_t, ws_n = _ws(fht_workspace_bytes(dt, h, w, k), img.device, ws)
+        rc = lib().fhtp_fht_bands(img.data_ptr(), dt, h, w, k, tables.data_ptr(), _ptr(ws_t),
+                                  ws_n, _stream_ptr(stream))
     _check(rc, "fht_bands")
     return tables
 
@@ -238,13 +277,14 @@ def polyline_dp(tables, h: int, w: int, k: int, bend: Optional[int] = None,
     torch = _torch()
     _require_device(tables, "tables")
     b = make_bend(bend, gamma)
-    if score is None:
-        score = torch.empty(1, dtype=torch.int32, device=tables.device)
-    if xs is None:
-        xs = torch.empty(k + 1, dtype=torch.int32, device=tables.device)
-    ws_t, ws_n = _ws(dp_workspace_bytes(h, w, k, b), tables.device, ws)
-    rc = lib().fhtp_polyline_dp(tables.data_ptr(), h, w, k, b, _ptr(ws_t), ws_n,
-                                score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
+    with _on_stream(stream):
+        if score is None:
+            score = torch.empty(1, dtype=torch.int32, device=tables.device)
+        if xs is None:
+            xs = torch.empty(k + 1, dtype=torch.int32, device=tables.device)
+        ws_t, ws_n = _ws(dp_workspace_bytes(h, w, k, b), tables.device, ws)
+        rc = lib().fhtp_polyline_dp(tables.data_ptr(), h, w, k, b, _ptr(ws_t), ws_n,
+                                    score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
     _check(rc, "polyline_dp")
     return score, xs
 
@@ -257,13 +297,14 @@ def detect_polyline(img, k: int, bend: Optional[int] = None, gamma: Optional[flo
     h, w = img.shape
     dt = _dtype_code(img)
     b = make_bend(bend, gamma)
-    if score is None:
-        score = torch.empty(1, dtype=torch.int32, device=img.device)
-    if xs is None:
-        xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
-    ws_t, ws_n = _ws(detect_workspace_bytes(dt, h, w, k, b), img.device, ws)
-    rc = lib().fhtp_detect_polyline(img.data_ptr(), dt, h, w, k, b, _ptr(ws_t), ws_n,
-                                    score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
+    with _on_stream(stream):
+        if score is None:
+            score = torch.empty(1, dtype=torch.int32, device=img.device)
+        if xs is None:
+            xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
+        ws_t, ws_n = _ws(detect_workspace_bytes(dt, h, w, k, b), img.device, ws)
+        rc = lib().fhtp_detect_polyline(img.data_ptr(), dt, h, w, k, b, _ptr(ws_t), ws_n,
+                                        score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
     _check(rc, "detect_polyline")
     return score, xs
 
@@ -274,10 +315,11 @@ def prepare_image(img, smooth_radius: int = 0, horizontal: bool = False, out=Non
     _require_device(img, "img")
     h, w = img.shape
     shape = (w, h) if horizontal else (h, w)
-    if out is None:
-        out = torch.empty(shape, dtype=img.dtype, device=img.device)
-    rc = lib().fhtp_prepare_image(img.data_ptr(), _dtype_code(img), h, w, int(smooth_radius),
-                                  int(bool(horizontal)), out.data_ptr(), _stream_ptr(stream))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty(shape, dtype=img.dtype, device=img.device)
+        rc = lib().fhtp_prepare_image(img.data_ptr(), _dtype_code(img), h, w, int(smooth_radius),
+                                      int(bool(horizontal)), out.data_ptr(), _stream_ptr(stream))
     _check(rc, "prepare_image")
     return out
 
@@ -296,13 +338,15 @@ def detect_polyline_ex(img, k: int, bend: Optional[int] = None, gamma: Optional[
     dt = _dtype_code(img)
     b = make_bend(bend, gamma)
     opt = make_options(smooth_radius, horizontal, pin)
-    if score is None:
-        score = torch.empty(1, dtype=torch.int32, device=img.device)
-    if xs is None:
-        xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
-    ws_t, ws_n = _ws(detect_ex_workspace_bytes(dt, h, w, k, b, opt), img.device, ws)
-    rc = lib().fhtp_detect_polyline_ex(img.data_ptr(), dt, h, w, k, b, C.byref(opt), _ptr(ws_t),
-                                       ws_n, score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
+    with _on_stream(stream):
+        if score is None:
+            score = torch.empty(1, dtype=torch.int32, device=img.device)
+        if xs is None:
+            xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
+        ws_t, ws_n = _ws(detect_ex_workspace_bytes(dt, h, w, k, b, opt), img.device, ws)
+        rc = lib().fhtp_detect_polyline_ex(img.data_ptr(), dt, h, w, k, b, C.byref(opt),
+                                           _ptr(ws_t), ws_n, score.data_ptr(), xs.data_ptr(),
+                                           _stream_ptr(stream))
     _check(rc, "detect_polyline_ex")
     return score, xs
 
@@ -338,11 +382,12 @@ def detect_batch(images, ks, bends=None, gammas=None, ws=None, scores=None, xss=
     torch = _torch()
     if len(images) == 0:
         return []
-    jobs, keep = make_jobs(images, ks, bends, gammas, scores, xss)
-    nbytes = batch_workspace_bytes(jobs)
-    ws_t, ws_n = _ws(nbytes, images[0].device, ws)
-    arr = (Job * len(jobs))(*jobs)
-    rc = lib().fhtp_detect_batch(arr, len(jobs), _ptr(ws_t), ws_n, _stream_ptr(stream))
+    with _on_stream(stream):
+        jobs, keep = make_jobs(images, ks, bends, gammas, scores, xss)
+        nbytes = batch_workspace_bytes(jobs)
+        ws_t, ws_n = _ws(nbytes, images[0].device, ws)
+        arr = (Job * len(jobs))(*jobs)
+        rc = lib().fhtp_detect_batch(arr, len(jobs), _ptr(ws_t), ws_n, _stream_ptr(stream))
     _check(rc, "detect_batch")
     return keep
 

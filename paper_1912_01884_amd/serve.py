@@ -59,6 +59,7 @@ class Request:
     done: float = math.nan
     nbytes: int = 0               # arena bytes while in flight
     error: Optional[str] = None
+    producer: Any = None          # stream current at submit (GPU backends), waited on at launch
 
     @property
     def latency(self) -> float:
@@ -149,6 +150,9 @@ class Server:
                          f"{self.arena.capacity}")
             self.rejected += 1
             return False
+        on_submit = getattr(self.backend, "on_submit", None)
+        if on_submit is not None:
+            on_submit(req)
         self.waiting.append(req)
         return True
 
@@ -194,7 +198,17 @@ class Server:
         now = self.clock()
         for r in take:
             r.admitted = now
-        handle = self.backend.launch(take, off, total, stream)
+        try:
+            handle = self.backend.launch(take, off, total, stream)
+        except BaseException:
+            # nothing of the group runs: give back its memory and stream and
+            # put its requests back at the head of the queue, in order
+            self.arena.free(off, total)
+            self._free_streams.insert(0, stream)
+            for r in reversed(take):
+                r.admitted = math.nan
+                self.waiting.appendleft(r)
+            raise
         self.inflight.append(_Group(take, off, total, stream, handle))
         self.groups_launched += 1
         return True
@@ -211,6 +225,24 @@ class Server:
 
 
 # ---- the GPU backend ---------------------------------------------------------
+
+def order_after_submitter(torch, s, reqs: List[Request], device) -> None:
+    """Order the detections on stream `s` after the request tensors' producers.
+
+    The images, scores and vertex buffers may have been filled or allocated
+    asynchronously on the stream that was current when the request was
+    submitted (`Request.producer`): `s` waits for each such stream, once per
+    distinct stream (without a recorded producer, for the stream current now).
+    The tensors themselves cannot be freed while the detection runs: the
+    server holds its requests until their completion event has fired.
+    """
+    seen = set()
+    for r in reqs:
+        p = r.producer if r.producer is not None else torch.cuda.current_stream(device)
+        if p.cuda_stream not in seen:
+            seen.add(p.cuda_stream)
+            s.wait_stream(p)
+
 
 class FhtpBackend:
     """Arena in device memory, streams and events; groups run fhtp_detect_batch."""
@@ -239,6 +271,9 @@ class FhtpBackend:
     def capacity(self) -> int:
         return self.arena.numel()
 
+    def on_submit(self, r: Request) -> None:
+        r.producer = self.torch.cuda.current_stream(self.device)
+
     def _job(self, r: Request):
         F = self.fhtp
         h, w = r.img.shape
@@ -255,6 +290,7 @@ class FhtpBackend:
         jobs = [self._job(r) for r in reqs]
         arr = (self.fhtp.Job * len(jobs))(*jobs)
         s = self.streams[stream]
+        order_after_submitter(self.torch, s, reqs, self.device)
         rc = self.L.fhtp_detect_batch(arr, len(jobs), C.c_void_p(self.base + offset), nbytes,
                                       C.c_void_p(s.cuda_stream))
         self.fhtp._check(rc, "detect_batch")
@@ -294,6 +330,7 @@ class PlainServer:
         if req.nbytes > self.ws.numel():
             req.error = "request larger than the workspace"
             return False
+        req.producer = self.torch.cuda.current_stream(self.device)
         self.waiting.append(req)
         return True
 
@@ -312,6 +349,7 @@ class PlainServer:
             r.admitted = self.clock()
             F = self.fhtp
             h, w = r.img.shape
+            order_after_submitter(self.torch, self.stream, [r], self.device)
             rc = self.L.fhtp_detect_polyline(
                 C.c_void_p(r.img.data_ptr()), F._dtype_code(r.img), h, w, r.k,
                 F.make_bend(r.bend, r.gamma), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),

@@ -249,3 +249,12 @@ def test_detect_ex_workspace_sizes():
     assert sm == plain + (256 * 300 + 255) // 256 * 256
     hz = fhtp.detect_ex_workspace_bytes(1, 300, 256, 4, b, fhtp.make_options(horizontal=True))
     assert hz == fhtp.detect_workspace_bytes(1, 256, 300, 4, b) + (2 * 256 * 300 + 255) // 256 * 256
+
+
+def test_timing_hook_is_host_only_when_nothing_ran():
+    from paper_1912_01884_amd import fhtp
+    fhtp.timing_start()
+    assert fhtp.timing_stop() == {}
+    L = fhtp.lib()
+    assert L.fhtp_timing_stop(None, 4, None) == fhtp.ERR_NULL
+

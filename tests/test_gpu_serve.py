@@ -116,3 +116,36 @@ def test_open_loop_server_and_plain_agree(dev, mix):
     for r in reqs:
         assert (int(host(r.score)[0]), host(r.xs).tolist()) == alone[r.rid]
 
+
+
+def test_requests_made_on_a_side_stream_after_the_server_starts(dev, mix):
+    """Inputs and outputs produced asynchronously on the submitting stream are waited for."""
+    from paper_1912_01884_amd.serve import FhtpBackend, PlainServer, Request, Server
+    batch, imgs = mix
+    alone = _alone(batch, imgs)
+    srv = Server(FhtpBackend(dev, arena_bytes=2 << 30, streams=3), streams=3, max_batch=8)
+    plain = PlainServer(dev, max_request_bytes=1 << 28)
+    side = torch.cuda.Stream(dev)
+    announce("serve 12 requests whose tensors are filled on a side stream")
+    for server in (srv, plain):
+        reqs = []
+        with torch.cuda.stream(side):
+            # a long kernel first, so that the copies really are still pending at submit
+            junk = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+            junk.fill_(3)
+            for rid, q in enumerate(range(12)):
+                s = batch[q]
+                img = torch.empty_like(imgs[q])
+                img.copy_(imgs[q])
+                reqs.append(Request(img=img, k=s.k, bend=s.bend,
+                                    score=torch.full((1,), -7, dtype=torch.int32, device=dev),
+                                    xs=torch.full((s.k + 1,), -7, dtype=torch.int32, device=dev),
+                                    rid=rid))
+            for r in reqs:
+                assert server.submit(r), r.error
+            server.poll()
+        server.drain(timeout=60)
+        torch.cuda.synchronize()
+        del junk
+        for r in reqs:
+            assert (int(host(r.score)[0]), host(r.xs).tolist()) == alone[r.rid], r.rid

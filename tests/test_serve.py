@@ -233,3 +233,38 @@ def test_poisson_rate():
     arr = poisson_arrivals(1000.0, 20000, 3)
     assert abs(arr[-1] - 20.0) < 0.6  # mean gap 1 ms
     assert poisson_arrivals(float("inf"), 5, 3) == [0.0] * 5
+
+
+def test_failed_launch_gives_back_memory_and_stream_and_requeues():
+    """A backend launch that raises leaves the server as it was before admission."""
+
+    class Flaky(SimBackend):
+        def __init__(self, *a, fail=1, **kw):
+            super().__init__(*a, **kw)
+            self.fail = fail
+
+        def launch(self, reqs, offset, nbytes, stream):
+            if self.fail > 0:
+                self.fail -= 1
+                raise RuntimeError("launch refused")
+            return super().launch(reqs, offset, nbytes, stream)
+
+    clock = Clock()
+    be = Flaky(clock, capacity=1 << 20)
+    srv = Server(be, streams=2, max_batch=4, clock=clock)
+    reqs = [_req(i, 1000) for i in range(6)]
+    for r in reqs:
+        srv.submit(r)
+    with pytest.raises(RuntimeError, match="launch refused"):
+        srv.poll()
+    assert srv.arena.used == 0 and srv.arena.free_blocks() == [(0, srv.arena.capacity)]
+    assert sorted(srv._free_streams) == [0, 1]
+    assert [r.rid for r in srv.waiting] == list(range(6))  # back at the head, in order
+    assert all(math.isnan(r.admitted) for r in reqs)
+    done = []
+    while not srv.idle():
+        done += srv.poll()
+        clock.t += 1e-4
+    assert sorted(r.rid for r in done) == list(range(6))
+    assert [rid for g in be.launches for rid in g] == list(range(6))
+    assert srv.arena.used == 0
