@@ -417,9 +417,9 @@ def summarize_trace(folder):
     starts = [q for q, e in enumerate(seq) if e[2].startswith("fht_reg_kernel")]
     for q0 in reversed(starts):
         q1 = next((q for q in range(q0, len(seq)) if seq[q][2].startswith("walk")), None)
-        if q1 is None:
-            continue
-        print("\nOne detection (the last one traced; kernels in launch order):\n")
+        if q1 is None or any("true>" in e[2] for e in seq[q0:q1 + 1]):
+            continue  # incomplete, or a through-point query (pinned kernels)
+        print("\nOne detection (the last unpinned one traced; kernels in launch order):\n")
         run = {}
         order = []
         for e in seq[q0:q1 + 1]:
@@ -453,10 +453,12 @@ def summarize_counters(fetch_dir, write_dir):
 
     fetch = per_kernel(fetch_dir, "FETCH_SIZE")
     write = per_kernel(write_dir, "WRITE_SIZE")
-    copy_f = next(v for k, v in fetch.items() if "copyBuffer" in k or "copy" in k.lower())
-    fill_w = next(v for k, v in write.items() if "Fill" in k or "fill" in k)
-    sf = copy_f[-1] / mib256
-    sw = fill_w[-1] / mib256
+    # the probe's 256 MiB device copy is the largest copyBuffer dispatch (the
+    # image's upload from the host is another one), its fill the FillFunctor one
+    copy_f = max(x for k, v in fetch.items() if "copyBuffer" in k for x in v)
+    fill_w = max(x for k, v in write.items() if "FillFunctor" in k for x in v)
+    sf = copy_f / mib256
+    sw = fill_w / mib256
     print(f"Calibration: FETCH_SIZE reads {sf:.4f} x the bytes the copy fetched, "
           f"WRITE_SIZE {sw:.4f} x the bytes the fill wrote.\n")
     print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetched (scaled) | "

@@ -266,15 +266,17 @@ int fhtp_plan_destroy(fhtp_plan plan);
  * Kernel timing, for benchmarks and tuning (not part of the method).
  *
  * fhtp_timing_start: clears earlier records and turns timing on for the
- *   whole process: from then on every kernel launch the library makes outside
- *   graph capture is bracketed by two HIP events recorded on its stream (the
- *   brackets add a little time of their own between launches).
+ *   whole process: from then on every run of consecutive launches of one
+ *   kernel family that the library makes outside graph capture (a single
+ *   launch, or for example the run of two-step DP launches of a detection) is
+ *   bracketed by two HIP events recorded on its stream.  A bracket covers its
+ *   launches and the gaps between them, plus a little time of its own.
  * fhtp_timing_stop: turns timing off, waits for every recorded event, and
  *   returns one entry per kernel family in order of first launch: the family
  *   name ("fht_reg_kernel", "fht_combine_kernel", "dp_pair_fixed",
  *   "dp_step_fixed", "dp_step_generic", "argmax_table", "walk",
  *   "angle_windows", "prep_kernel", ...), its launch count and the summed
- *   elapsed time between its brackets in milliseconds.  Up to `cap` entries
+ *   elapsed time of its brackets in milliseconds.  Up to `cap` entries
  *   are written to `out` (host memory); *count receives the number of
  *   families.  FHTP_ERR_HIP if an event could not be read (the entries are
  *   then incomplete).  Host calls; not thread-safe against concurrent

@@ -1327,6 +1327,11 @@ DpClass class_of(const DpJobSpec& j) {
     return c;
 }
 
+// Kernel family of a class's single-step launches (for the timing brackets).
+const char* step_family(const DpClass& c) {
+    return c.kind == (int)WindowKind::Fixed ? "dp_step_fixed" : "dp_step_generic";
+}
+
 int items_y_of(const Geometry& g, int dc) {
     const int chunks = (g.D + dc - 1) / dc;
     return (chunks + kWaves - 1) / kWaves;
@@ -1334,7 +1339,6 @@ int items_y_of(const Geometry& g, int dc) {
 
 template <int B, typename AT, int CAP>
 void launch_fixed_b(int dc, hipStream_t s, const DpPack<CAP>& pk) {
-    TimedLaunch tl("dp_step_fixed", s);
     if (dc == 8)
         hipLaunchKernelGGL((dp_step_fixed<B, 8, AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
     else
@@ -1344,7 +1348,6 @@ void launch_fixed_b(int dc, hipStream_t s, const DpPack<CAP>& pk) {
 template <typename AT, int CAP>
 hipError_t launch_step(const DpClass& c, hipStream_t s, const DpPack<CAP>& pk) {
     if (c.kind != (int)WindowKind::Fixed) {
-        TimedLaunch tl("dp_step_generic", s);
         hipLaunchKernelGGL((dp_step_generic<AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
         return hipSuccess;
     }
@@ -1387,6 +1390,7 @@ template <typename AT, int CAP>
 hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
     int max_steps = 0;
     for (const DpJobSpec* J : jobs) max_steps = std::max(max_steps, J->g.k - 1);
+    TimedLaunch tl(step_family(c), s, max_steps);
     for (int st = 0; st < max_steps; ++st) {
         DpPack<CAP> pk{};
         long long total = 0;
@@ -1428,12 +1432,10 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
 template <typename AT, int CAP, bool PIN>
 hipError_t launch_pair_p(int bound, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
 #define FHTP_B(BB)                                                                               \
-    case BB: {                                                                                   \
-        TimedLaunch tl("dp_pair_fixed", s);                                                      \
+    case BB:                                                                                     \
         hipLaunchKernelGGL((dp_pair_fixed<BB, AT, CAP, PIN>), dim3(grid), dim3(64 * kPairWaves), \
                            0, s, pk);                                                            \
-        return hipSuccess;                                                                       \
-    }
+        return hipSuccess;
     switch (bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
         FHTP_B(9) FHTP_B(10) FHTP_B(11) FHTP_B(12) FHTP_B(13) FHTP_B(14) FHTP_B(15) FHTP_B(16)
@@ -1520,9 +1522,12 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
         }
         pk.count = cnt;
         pk.total = (int)total;
+        TimedLaunch tl(step_family(c), s);
         hipError_t e = launch_step<AT, CAP>(c, s, pk);
         if (e != hipSuccess) return e;
     }
+    // one timing bracket around the whole run of pair launches
+    TimedLaunch tl_pairs(Q > 0 ? "dp_pair_fixed" : nullptr, s, Q);
     for (int L = 0; L < Q; ++L) {
         DpPairPack<CAP> pk{};
         long long total = 0;
@@ -1588,6 +1593,8 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
     }
     pk.count = cnt;
     pk.total = (int)total;
+    tl_pairs.close();
+    TimedLaunch tl(step_family(c), s);
     return launch_step<AT, CAP>(c, s, pk);
 }
 

@@ -18,19 +18,24 @@ struct Geometry {
     int pitch;  // row pitch (elements) of the DP planes: w rounded up to 64
 };
 
-// Brackets one kernel launch with events while benchmark timing is on
-// (fhtp_timing_start); a no-op otherwise.  Construct it right before the
-// launch, on the launch's stream; the bracket closes when it goes out of scope.
+// Brackets a run of `launches` consecutive kernel launches of one family on
+// one stream with two events while benchmark timing is on (fhtp_timing_start);
+// a no-op otherwise, or when family is null.  Construct it right before the
+// first launch; the bracket closes at close() or when it goes out of scope,
+// which must come right after the last launch.  One bracket per run rather
+// than per launch: every event is a packet of its own between two kernels.
 class TimedLaunch {
 public:
-    TimedLaunch(const char* family, hipStream_t s);
-    ~TimedLaunch();
+    TimedLaunch(const char* family, hipStream_t s, int launches = 1);
+    ~TimedLaunch() { close(); }
+    void close();
     TimedLaunch(const TimedLaunch&) = delete;
     TimedLaunch& operator=(const TimedLaunch&) = delete;
 
 private:
     const char* family_;
     hipStream_t stream_;
+    int launches_;
     hipEvent_t begin_ = nullptr;
 };
 

@@ -21,12 +21,12 @@ namespace {
 
 struct Bracket {
     const char* family;
+    int launches;
     hipEvent_t begin, end;
 };
 
 std::atomic<bool> g_on{false};
 std::mutex g_mu;
-std::vector<Bracket> g_open;     // begun, not ended (one per thread at a time in practice)
 std::vector<Bracket> g_done;
 std::vector<hipEvent_t> g_pool;  // events of earlier runs, reused
 
@@ -55,8 +55,9 @@ bool capturing(hipStream_t s) {
 
 }  // namespace
 
-TimedLaunch::TimedLaunch(const char* family, hipStream_t s) : family_(family), stream_(s) {
-    if (!g_on.load(std::memory_order_relaxed) || capturing(s)) return;
+TimedLaunch::TimedLaunch(const char* family, hipStream_t s, int launches)
+    : family_(family), stream_(s), launches_(launches) {
+    if (!family || launches <= 0 || !g_on.load(std::memory_order_relaxed) || capturing(s)) return;
     std::lock_guard<std::mutex> lock(g_mu);
     begin_ = take_event();
     if (begin_ && hipEventRecord(begin_, s) != hipSuccess) {
@@ -66,7 +67,7 @@ TimedLaunch::TimedLaunch(const char* family, hipStream_t s) : family_(family), s
     }
 }
 
-TimedLaunch::~TimedLaunch() {
+void TimedLaunch::close() {
     if (!begin_) return;
     std::lock_guard<std::mutex> lock(g_mu);
     hipEvent_t end = take_event();
@@ -74,9 +75,10 @@ TimedLaunch::~TimedLaunch() {
         (void)hipGetLastError();
         g_pool.push_back(begin_);
         if (end) g_pool.push_back(end);
-        return;
+    } else {
+        g_done.push_back(Bracket{family_, launches_, begin_, end});
     }
-    g_done.push_back(Bracket{family_, begin_, end});
+    begin_ = nullptr;
 }
 
 }  // namespace fhtp
@@ -114,7 +116,7 @@ int fhtp_timing_stop(fhtp_kernel_time* out, int cap, int* count) {
             std::strncpy(t.name, b.family, sizeof(t.name) - 1);
             fam.push_back(t);
         }
-        fam[q].launches += 1;
+        fam[q].launches += b.launches;
         fam[q].total_ms += ms;
         fhtp::g_pool.push_back(b.begin);
         fhtp::g_pool.push_back(b.end);
