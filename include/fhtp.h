@@ -211,10 +211,13 @@ int fhtp_detect_polyline_ex(const void* img, fhtp_dtype dtype, int h, int w, int
  *        pointers inside are device pointers as in fhtp_detect_polyline.
  * ws:    device scratch, fhtp_batch_workspace_bytes(...) bytes.
  * Streams: part of the batch (the images with bands of more than 128 rows)
- *        may run on a library-owned stream of the current device, forked from
- *        `stream` and joined back into it with events; all results are still
- *        complete once `stream` has been synchronised, and the fork/join is
- *        valid under graph capture.
+ *        may run on a second, library-owned stream, forked from `stream` and
+ *        joined back into it with events; all results are still complete once
+ *        `stream` has been synchronised, and the fork/join is valid under
+ *        graph capture.  Each caller stream (per device) gets its own second
+ *        stream, created on first use outside capture and kept until the
+ *        process ends; a plan owns one of its own.  Batches on different
+ *        caller streams therefore never share a second stream.
  * Errors: the first invalid job's code; nothing is enqueued in that case.
  * ------------------------------------------------------------------------- */
 typedef struct {

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -108,17 +110,38 @@ DpLayout dp_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, size_t base)
     return L;
 }
 
+// Workspace of a whole detection: the band tables (narrow ones when the
+// pixels allow: bands 0 .. k-2 as uint16, then the last band as int32), the
+// FHT's scratch for tall bands, then the DP's buffers.
 struct DetectLayout {
-    size_t tables, scratch;
+    size_t tables, wide, scratch;
+    int narrow;  // bands stored as uint16
     DpLayout dp;
 };
 
-DetectLayout detect_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl) {
+DetectLayout detect_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, fhtp_dtype dtype) {
     DetectLayout L;
+    const size_t band = (size_t)g.D * (size_t)g.W;
     L.tables = 0;
-    L.scratch = align_up((size_t)g.k * g.D * (size_t)g.W * sizeof(int32_t));
+    L.narrow = fhtp::narrow_tables_apply(g, (int)dtype) ? g.k - 1 : 0;
+    L.wide = align_up(L.tables + (size_t)L.narrow * band * sizeof(uint16_t));
+    L.scratch = align_up(L.wide + (size_t)(g.k - L.narrow) * band * sizeof(int32_t));
     L.dp = dp_layout(g, pl, align_up(L.scratch + fhtp::fht_scratch_bytes(g)));
     return L;
+}
+
+fhtp::TableSet table_set(char* base, const DetectLayout& L) {
+    fhtp::TableSet t;
+    t.narrow = L.narrow;
+    t.tab16 = L.narrow ? reinterpret_cast<uint16_t*>(base + L.tables) : nullptr;
+    t.wide = reinterpret_cast<int32_t*>(base + L.wide);
+    return t;
+}
+
+fhtp::TableSet wide_tables(const int32_t* tables) {
+    fhtp::TableSet t;
+    t.wide = const_cast<int32_t*>(tables);
+    return t;
 }
 
 fhtp::DpBuffers dp_buffers(char* ws, const DpLayout& L) {
@@ -202,7 +225,7 @@ int fhtp_fht_bands(const void* img, fhtp_dtype dtype, int h, int w, int k, int32
     if (rc == FHTP_OK) rc = check_ws(ws, ws_bytes, fhtp::fht_scratch_bytes(g));
     if (rc != FHTP_OK) return rc;
     (void)hipGetLastError();
-    return hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, ws,
+    return hip_status(fhtp::launch_fht(img, (int)dtype, g, wide_tables(tables), ws,
                                        static_cast<hipStream_t>(stream)),
                       "fht_bands");
 }
@@ -230,8 +253,9 @@ int fhtp_polyline_dp(const int32_t* tables, int h, int w, int k, fhtp_bend bend,
     rc = check_ws(ws, ws_bytes, L.end);
     if (rc != FHTP_OK) return rc;
     (void)hipGetLastError();
-    return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(static_cast<char*>(ws), L), score,
-                                      xs, static_cast<hipStream_t>(stream)),
+    return hip_status(fhtp::launch_dp(wide_tables(tables), g, pl,
+                                      dp_buffers(static_cast<char*>(ws), L), score, xs,
+                                      static_cast<hipStream_t>(stream)),
                       "polyline_dp");
 }
 
@@ -244,7 +268,7 @@ int fhtp_detect_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend
     if (rc == FHTP_OK) rc = pixels(dtype, h);
     if (rc == FHTP_OK) rc = plan(g, bend, &pl);
     if (rc != FHTP_OK) return rc;
-    *bytes = detect_layout(g, pl).dp.end;
+    *bytes = detect_layout(g, pl, dtype).dp.end;
     return FHTP_OK;
 }
 
@@ -257,11 +281,11 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
     if (rc == FHTP_OK) rc = pixels(dtype, h);
     if (rc == FHTP_OK) rc = plan(g, bend, &pl);
     if (rc != FHTP_OK) return rc;
-    const DetectLayout L = detect_layout(g, pl);
+    const DetectLayout L = detect_layout(g, pl, dtype);
     rc = check_ws(ws, ws_bytes, L.dp.end);
     if (rc != FHTP_OK) return rc;
     char* base = static_cast<char*>(ws);
-    int32_t* tables = reinterpret_cast<int32_t*>(base + L.tables);
+    const fhtp::TableSet tables = table_set(base, L);
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
     rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s),
@@ -304,7 +328,7 @@ int plan_ex(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend, const fhtp_op
     e->prep = o.horizontal || o.smooth_radius > 0;
     const size_t bpp = dtype == FHTP_U8 ? 1 : 2;
     e->prep_bytes = e->prep ? align_up((size_t)h * (size_t)w * bpp) : 0;
-    e->L = detect_layout(e->g, e->pl);
+    e->L = detect_layout(e->g, e->pl, dtype);
     return FHTP_OK;
 }
 
@@ -354,7 +378,7 @@ int fhtp_detect_polyline_ex(const void* img, fhtp_dtype dtype, int h, int w, int
         det = base;
         base += e.prep_bytes;
     }
-    int32_t* tables = reinterpret_cast<int32_t*>(base + e.L.tables);
+    const fhtp::TableSet tables = table_set(base, e.L);
     rc = hip_status(fhtp::launch_fht(det, (int)dtype, e.g, tables, base + e.L.scratch, s),
                     "detect_polyline_ex/fht");
     if (rc != FHTP_OK) return rc;
@@ -392,7 +416,7 @@ int plan_batch(const fhtp_job* jobs, int count, std::vector<BatchEntry>* out, si
             g_detail = buf;
             return rc;
         }
-        e.L = detect_layout(e.g, e.pl);
+        e.L = detect_layout(e.g, e.pl, (fhtp_dtype)J.dtype);
         e.offset = off;
         off = align_up(off + e.L.dp.end);
         out->push_back(e);
@@ -415,43 +439,73 @@ int fhtp_batch_workspace_bytes(const fhtp_job* jobs, int count, size_t* bytes) {
 
 namespace {
 
-// A second stream per device for batches: the images whose tall bands take
-// the two-pass FHT and 16-bit back-pointers run their whole pipeline there,
-// the others on the caller's stream, so the two chains of dependent DP steps
-// (each bound by latency, not by the chip) overlap.  The caller's stream
-// forks to it with an event and joins back with another, so graph capture
-// sees a closed fork/join.  Created on first use outside graph capture (a call
-// under capture that finds it missing runs on one stream) and kept until the
-// process ends; streams keep the default priority.
-constexpr int kMaxDevices = 64;
-
+// A second stream for batches: the images whose tall bands take the two-pass
+// FHT and 16-bit back-pointers run their whole pipeline there, the others on
+// the caller's stream, so the two chains of dependent DP steps (each bound by
+// latency, not by the chip) overlap.  The caller's stream forks to it with an
+// event and joins back with another, so graph capture sees a closed
+// fork/join.  Eager calls get one second stream per caller stream (created on
+// first use outside graph capture and kept until the process ends), so
+// batches on different caller streams never share one; a plan owns its own,
+// created before its capture opens.  Streams keep the default priority.
 struct Aux {
-    std::mutex mu;
-    bool tried = false;
+    std::mutex mu;  // calls that share this Aux (ordered on one caller stream)
     bool ok = false;
     hipStream_t stream = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
 
-Aux g_aux[kMaxDevices];
+bool aux_init(Aux* a) {
+    a->ok = hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&a->fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&a->join, hipEventDisableTiming) == hipSuccess;
+    (void)hipGetLastError();
+    return a->ok;
+}
 
-Aux* aux_for_current_device(hipStream_t s) {
+void aux_release(Aux* a) {
+    if (a->fork) (void)hipEventDestroy(a->fork);
+    if (a->join) (void)hipEventDestroy(a->join);
+    if (a->stream) (void)hipStreamDestroy(a->stream);
+    a->fork = a->join = nullptr;
+    a->stream = nullptr;
+    a->ok = false;
+}
+
+struct AuxKey {
+    int device;
+    hipStream_t caller;
+    bool operator<(const AuxKey& o) const {
+        return device != o.device ? device < o.device : caller < o.caller;
+    }
+};
+
+std::mutex g_aux_mu;  // guards the map only, never held across launches
+std::map<AuxKey, std::unique_ptr<Aux>> g_aux;
+
+// The second stream of eager batches on caller stream s of the current
+// device, or null (then the batch runs on s alone): under capture a missing
+// one is not created.
+Aux* aux_for_caller(hipStream_t s) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-    Aux& a = g_aux[dev];
-    std::lock_guard<std::mutex> lock(a.mu);
-    if (a.tried) return a.ok ? &a : nullptr;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_aux_mu);
+    auto it = g_aux.find(AuxKey{dev, s});
+    if (it != g_aux.end()) return it->second->ok ? it->second.get() : nullptr;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();
         return nullptr;
     }
-    a.tried = true;
-    a.ok = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&a.join, hipEventDisableTiming) == hipSuccess;
-    (void)hipGetLastError();
-    return a.ok ? &a : nullptr;
+    std::unique_ptr<Aux> a(new (std::nothrow) Aux);
+    if (!a) return nullptr;
+    aux_init(a.get());
+    Aux* out = a->ok ? a.get() : nullptr;
+    g_aux.emplace(AuxKey{dev, s}, std::move(a));
+    return out;
 }
 
 // FHT then DP of a subset of a batch on one stream.
@@ -470,7 +524,12 @@ int run_subset(const std::vector<fhtp::FhtJobSpec>& fj, const std::vector<fhtp::
 
 }  // namespace
 
-int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+
+// fhtp_detect_batch with an explicit second stream (`ax`; null: look one up
+// for the caller's stream).
+int detect_batch_on(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, void* stream,
+                    Aux* ax_given) {
     std::vector<BatchEntry> plan_v;
     size_t total = 0;
     int rc = plan_batch(jobs, count, &plan_v, &total);
@@ -483,7 +542,7 @@ int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes
     for (int q = 0; q < count; ++q) {
         const BatchEntry& e = plan_v[q];
         char* base = static_cast<char*>(ws) + e.offset;
-        int32_t* tables = reinterpret_cast<int32_t*>(base + e.L.tables);
+        const fhtp::TableSet tables = table_set(base, e.L);
         fj[q] = fhtp::FhtJobSpec{jobs[q].img, (int)jobs[q].dtype, e.g, tables, base + e.L.scratch};
         dj[q] = fhtp::DpJobSpec{tables, e.g, e.pl, dp_buffers(base, e.L.dp), jobs[q].score,
                                 jobs[q].xs};
@@ -492,7 +551,9 @@ int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes
     (void)hipGetLastError();
     std::vector<int> tall, rest;
     for (int q = 0; q < count; ++q) (dj[q].plan.a16 ? tall : rest).push_back(q);
-    Aux* ax = (!tall.empty() && !rest.empty()) ? aux_for_current_device(s) : nullptr;
+    Aux* ax = nullptr;
+    if (!tall.empty() && !rest.empty()) ax = ax_given ? ax_given : aux_for_caller(s);
+    if (ax && !ax->ok) ax = nullptr;
     if (!ax) {
         rc = hip_status(fhtp::launch_fht_jobs(fj.data(), count, s), "detect_batch/fht");
         if (rc != FHTP_OK) return rc;
@@ -511,6 +572,12 @@ int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes
     return rc_tall != FHTP_OK ? rc_tall : rc_rest != FHTP_OK ? rc_rest : rc_join;
 }
 
+}  // namespace
+
+int fhtp_detect_batch(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, void* stream) {
+    return detect_batch_on(jobs, count, ws, ws_bytes, stream, nullptr);
+}
+
 }  // extern "C"
 
 // A plan: the jobs of one fhtp_detect_batch call, their workspace, and the
@@ -522,6 +589,7 @@ struct fhtp_plan_s {
     int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    Aux aux;  // the plan's own second stream (created by the first capture)
 };
 
 namespace {
@@ -584,12 +652,15 @@ int fhtp_plan_capture(fhtp_plan p) {
         hipStream_t cs = nullptr;
         int rc = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "plan_capture");
         if (rc != FHTP_OK) return rc;
-        // the batch's second stream must exist before the capture opens
-        (void)aux_for_current_device(cs);
+        // the plan's second stream must exist before the capture opens
+        if (!p->aux.ok) {
+            aux_release(&p->aux);
+            aux_init(&p->aux);
+        }
         rc = hip_status(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "plan_capture");
         if (rc == FHTP_OK) {
-            const int rc_run =
-                fhtp_detect_batch(p->jobs.data(), (int)p->jobs.size(), p->ws, p->ws_bytes, cs);
+            const int rc_run = detect_batch_on(p->jobs.data(), (int)p->jobs.size(), p->ws,
+                                               p->ws_bytes, cs, p->aux.ok ? &p->aux : nullptr);
             hipGraph_t g = nullptr;
             const int rc_end = hip_status(hipStreamEndCapture(cs, &g), "plan_capture/end");
             rc = rc_run != FHTP_OK ? rc_run : rc_end;
@@ -610,7 +681,8 @@ int fhtp_plan_launch(fhtp_plan p, void* stream) {
     if (!p) return FHTP_ERR_NULL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!p->exec)
-        return fhtp_detect_batch(p->jobs.data(), (int)p->jobs.size(), p->ws, p->ws_bytes, s);
+        return detect_batch_on(p->jobs.data(), (int)p->jobs.size(), p->ws, p->ws_bytes, s,
+                               p->aux.ok ? &p->aux : nullptr);
     return hip_status(hipGraphLaunch(p->exec, s), "plan_launch");
 }
 
@@ -618,6 +690,7 @@ int fhtp_plan_destroy(fhtp_plan p) {
     if (!p) return FHTP_OK;
     const int rc = on_device(p->device, "plan_destroy", [&]() -> int {
         release_graph(p);
+        aux_release(&p->aux);
         return FHTP_OK;
     });
     delete p;

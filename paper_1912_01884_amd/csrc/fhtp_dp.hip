@@ -71,7 +71,7 @@ constexpr int kStoreScope = 16;
 // One image in one step launch.
 struct DpJob {
     const int32_t* vin;       // V_{i+1} (or the table H_{k-1}), rows d'+n-1
-    const int32_t* htab;      // H_i
+    const void* htab;         // H_i: int32, or uint16 for narrow tables (the kernel's TT)
     int32_t* vout;            // V_i (null on the image's last step)
     void* aout;               // A_{i+1} plane (null on the last step)
     unsigned long long* key;  // last step: one packed key per workgroup, else null
@@ -224,14 +224,26 @@ __device__ __forceinline__ void window_of(int n, int full, const int32_t* win, i
 
 // H_i(x' - d, d) for one output cell, 0 where the cell does not exist
 // (unconditional load, as load_v).
+template <typename TT>
 __device__ __forceinline__ int load_h(const DpJob& a, int xp, int d) {
     const int r = d + a.n - 1;
     const int x = xp - d;
     const bool ok = (unsigned)xp < (unsigned)a.w && (unsigned)r < (unsigned)(2 * a.n - 1) &&
                     (unsigned)x < (unsigned)a.w;
     const unsigned int off = ok ? (unsigned int)r * (unsigned int)a.h_pitch + (unsigned int)x : 0u;
-    const int v = a.htab[off];
+    const int v = (int)static_cast<const TT*>(a.htab)[off];
     return ok ? v : 0;
+}
+
+// One table cell through a buffer view, at byte offsets computed with the
+// table's element size: int32 tables, or uint16 narrow ones (zero-extended).
+template <typename TT>
+__device__ __forceinline__ int load_tab(__amdgpu_buffer_rsrc_t r, unsigned int voff,
+                                        unsigned int soff) {
+    if constexpr (sizeof(TT) == 2)
+        return (int)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
 }
 
 // The best cell of a thread on the last step: its packed key and the row
@@ -399,27 +411,27 @@ __device__ __forceinline__ bool wave_is_interior(const DpJob& a, int X0, int r0,
            X0 - (d0 + DC - 1) >= 0 && X0 + 63 - d0 < w;          // x = x' - d for every cell
 }
 
-template <int B, int DC, typename AT>
+template <int B, int DC, typename AT, typename TT>
 __device__ __forceinline__ Best fixed_interior(const DpJob& a, int X0, int r0, int d0) {
     constexpr int NV = DC + 2 * B;
+    constexpr unsigned int hsz = sizeof(TT);
     const int D = 2 * a.n - 1;
     const int xp = X0 + (int)(threadIdx.x & 63);
     const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
-    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
+    const unsigned int hp = (unsigned int)a.h_pitch * hsz;
     const __amdgpu_buffer_rsrc_t vr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<int32_t*>(a.vin) + (size_t)(r0 - B) * a.vin_pitch, (short)0, (int)(NV * vp),
         0x00020000);
     const __amdgpu_buffer_rsrc_t hr = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<int32_t*>(a.htab) + (size_t)r0 * a.h_pitch, (short)0, (int)(DC * hp),
-        0x00020000);
+        const_cast<TT*>(static_cast<const TT*>(a.htab)) + (size_t)r0 * a.h_pitch, (short)0,
+        (int)(DC * hp), 0x00020000);
     // cell j sits at column x' - d0 - j: one lane offset for the row group,
     // the column step as a constant
-    const unsigned int diag = (unsigned int)(xp - d0 - (DC - 1)) * 4u;
+    const unsigned int diag = (unsigned int)(xp - d0 - (DC - 1)) * hsz;
     int hv[DC], v[NV];
 #pragma unroll
     for (int j = 0; j < DC; ++j)
-        hv[j] = __builtin_amdgcn_raw_buffer_load_b32(hr, (int)(diag + (DC - 1 - j) * 4),
-                                                     (int)(j * hp), 0);
+        hv[j] = load_tab<TT>(hr, diag + (DC - 1 - j) * hsz, j * hp);
 #pragma unroll
     for (int j = 0; j < NV; ++j)
         v[j] = __builtin_amdgcn_raw_buffer_load_b32(vr, xp * 4, (int)(j * vp), 0);
@@ -437,6 +449,8 @@ __device__ __forceinline__ Best fixed_interior(const DpJob& a, int X0, int r0, i
     }
     const unsigned int op = (unsigned int)a.v_pitch * 4u;
     const unsigned int ap = (unsigned int)a.a_pitch * sizeof(AT);
+    // the V_i cells lie on the same diagonal as the table cells, at 4 bytes a cell
+    const unsigned int vdiag = (unsigned int)(xp - d0 - (DC - 1)) * 4u;
     const __amdgpu_buffer_rsrc_t orr = __builtin_amdgcn_make_buffer_rsrc(
         a.vout + (size_t)r0 * a.v_pitch, (short)0, (int)(DC * op), 0x00020000);
     const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
@@ -449,7 +463,7 @@ __device__ __forceinline__ Best fixed_interior(const DpJob& a, int X0, int r0, i
             __builtin_amdgcn_raw_buffer_store_b8((unsigned char)row, ar, xp, (int)(j * ap), kStoreScope);
         else
             __builtin_amdgcn_raw_buffer_store_b16((unsigned short)row, ar, xp * 2, (int)(j * ap), kStoreScope);
-        __builtin_amdgcn_raw_buffer_store_b32(val, orr, (int)(diag + (DC - 1 - j) * 4),
+        __builtin_amdgcn_raw_buffer_store_b32(val, orr, (int)(vdiag + (DC - 1 - j) * 4),
                                               (int)(j * op), kStoreScope);
     }
     return best;
@@ -464,7 +478,7 @@ __device__ __forceinline__ Best fixed_interior(const DpJob& a, int X0, int r0, i
 // that is never used, and offsets outside a view read 0); stores are masked
 // by ranges and every variable offset part sits in the lane offset, which the
 // hardware checks against the view's extent.
-template <int B, int DC, typename AT>
+template <int B, int DC, typename AT, typename TT>
 __device__ __forceinline__ Best fixed_general(const DpJob& a, int X0, int r0, int d0) {
     constexpr int NV = DC + 2 * B;
     constexpr int esz = (int)sizeof(AT);
@@ -474,13 +488,13 @@ __device__ __forceinline__ Best fixed_general(const DpJob& a, int X0, int r0, in
     const bool col_ok = xp < w;
 
     // H_i(x' - d, d), d = d0 + j: rows r0 + j, column x' - d.
-    const RowView hview = row_view(a.htab, a.h_pitch, 4, r0, DC, D);
-    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
-    const unsigned int hb = (unsigned int)(r0 - hview.base) * hp + (unsigned int)(xp - d0) * 4u;
+    constexpr unsigned int hsz = sizeof(TT);
+    const RowView hview = row_view(a.htab, a.h_pitch, (int)hsz, r0, DC, D);
+    const unsigned int hp = (unsigned int)a.h_pitch * hsz;
+    const unsigned int hb = (unsigned int)(r0 - hview.base) * hp + (unsigned int)(xp - d0) * hsz;
     int hv[DC];
 #pragma unroll
-    for (int j = 0; j < DC; ++j)
-        hv[j] = __builtin_amdgcn_raw_buffer_load_b32(hview.rs, (int)(hb + j * (hp - 4u)), 0, 0);
+    for (int j = 0; j < DC; ++j) hv[j] = load_tab<TT>(hview.rs, hb + j * (hp - hsz), 0);
     // V_{i+1}(x', d'), d' = d0 - B + q: rows r0 - B + q, column x'; a cell when
     // x' passes the pin, the row lies in [0, D) and x' + d' in [tlo, tlo + tlen).
     const VMask mk = vmask(w, a.vin_pin, a.vin_pin_x);
@@ -543,18 +557,20 @@ __device__ __forceinline__ Best fixed_general(const DpJob& a, int X0, int r0, in
     return best;
 }
 
-template <int B, int DC, typename AT>
+template <int B, int DC, typename AT, typename TT>
 __device__ __forceinline__ Best fixed_item(const DpJob& a, int bx, int by) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int X0 = bx * 64;
     const int r0 = (by * kWaves + wave) * DC;  // table row of this wave's first displacement
     const int d0 = r0 - (a.n - 1);
-    if (wave_is_interior<B, DC>(a, X0, r0, d0)) return fixed_interior<B, DC, AT>(a, X0, r0, d0);
-    return fixed_general<B, DC, AT>(a, X0, r0, d0);
+    if (wave_is_interior<B, DC>(a, X0, r0, d0))
+        return fixed_interior<B, DC, AT, TT>(a, X0, r0, d0);
+    return fixed_general<B, DC, AT, TT>(a, X0, r0, d0);
 }
 
-// Step with the mode-0 window fixed at compile time.
-template <int B, int DC, typename AT, int CAP>
+// Step with the mode-0 window fixed at compile time.  TT: the table's
+// element type (int32, or uint16 for narrow tables).
+template <int B, int DC, typename AT, int CAP, typename TT>
 __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
     // items of an image run down the displacement groups of one column tile
     // before the next tile, so the window rows shared by vertical neighbours
@@ -564,7 +580,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_fixed(DpPack<CAP> pk) {
     const DpJob& a = pk.job[j];
     const int local = it - a.item0;
     const int bx = local / a.items_y, by = local - bx * a.items_y;
-    const Best best = fixed_item<B, DC, AT>(a, bx, by);
+    const Best best = fixed_item<B, DC, AT, TT>(a, bx, by);
     finish(a, best, local);
 }
 
@@ -595,8 +611,8 @@ constexpr int kStrip = 16;                       // phase 1: displacements per t
 
 struct DpPairJob {
     const int32_t* vin;  // V_{i+2} (or the table H_{k-1}), rows d''+n-1
-    const int32_t* h1;   // H_{i+1}
-    const int32_t* h0;   // H_i
+    const void* h1;      // H_{i+1} (int32, or uint16 for narrow tables: the kernel's TT)
+    const void* h0;      // H_i
     int32_t* vout;       // V_i
     void* a1;            // A_{i+2} plane: at each cell of step i, the link after next
     void* a0;            // A_{i+1} plane
@@ -628,7 +644,7 @@ constexpr int kStripeTiles = 16;  // column tiles per stripe of the pair kernel'
 // the view's extent.
 // PIN: the through-point masks (a separate instantiation, so that unpinned
 // launches carry none of their instructions or registers).
-template <int B, typename AT, int CAP, bool PIN>
+template <int B, typename AT, int CAP, bool PIN, typename TT>
 __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP> pk) {
     constexpr int RM = kPairRows + 2 * B;  // rows of V_{i+1} the workgroup needs
     constexpr int NS = (RM + kStrip - 1) / kStrip;
@@ -675,24 +691,24 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     const int m0 = r0 - B;          // table row of mid[0]
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const unsigned int hp = (unsigned int)a.h_pitch * 4u;
+    constexpr unsigned int hsz = sizeof(TT);
+    const unsigned int hp = (unsigned int)a.h_pitch * hsz;
 
     // Phase 2's H_i(x' - d, d), issued first so that the loads overlap phase 1.
     const int xp = X0 + lane;
     const bool col_ok = xp < w;
     const int r2 = r0 + wave * kPairDC;
     const int d2 = r2 - (n - 1);
-    const RowView h0v = row_view(a.h0, a.h_pitch, 4, r2, kPairDC, D);
-    const unsigned int h0b = (unsigned int)(r2 - h0v.base) * hp + (unsigned int)(xp - d2) * 4u;
+    const RowView h0v = row_view(a.h0, a.h_pitch, (int)hsz, r2, kPairDC, D);
+    const unsigned int h0b = (unsigned int)(r2 - h0v.base) * hp + (unsigned int)(xp - d2) * hsz;
     int hv0[kPairDC];
 #pragma unroll
-    for (int j = 0; j < kPairDC; ++j)
-        hv0[j] = __builtin_amdgcn_raw_buffer_load_b32(h0v.rs, (int)(h0b + j * (hp - 4u)), 0, 0);
+    for (int j = 0; j < kPairDC; ++j) hv0[j] = load_tab<TT>(h0v.rs, h0b + j * (hp - hsz), 0);
 
     // Phase 1.  Views: V_{i+2} rows [m0 - B, m0 + NS*kStrip + B), H_{i+1} rows
     // [m0, m0 + RM), each clipped to [0, D).
     const RowView vv = row_view(a.vin, a.vin_pitch, 4, m0 - B, NS * kStrip + 2 * B, D);
-    const RowView h1v = row_view(a.h1, a.h_pitch, 4, m0, RM, D);
+    const RowView h1v = row_view(a.h1, a.h_pitch, (int)hsz, m0, RM, D);
     const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
     const unsigned int ap = (unsigned int)a.a_pitch * (unsigned int)esz;
     for (int t = threadIdx.x; t < NS * SC; t += 64 * kPairWaves) {
@@ -715,7 +731,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         const int jlo = max(-rs, X0 + c - w + 1);
         const int jhi = xs_ok ? D - rs : jlo;
         const unsigned int vb = (unsigned int)(rlo - vv.base) * vp + (unsigned int)xs * 4u;
-        const unsigned int hb = (unsigned int)(rs - h1v.base) * hp + (unsigned int)(X0 + c) * 4u;
+        const unsigned int hb = (unsigned int)(rs - h1v.base) * hp + (unsigned int)(X0 + c) * hsz;
         int* lrow = &mid[q0][LP + c];
         AT* nrow = &nxt[q0][LP + c];
         // A wave whose every load and cell is valid takes the unmasked copy.
@@ -738,7 +754,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
             int hv[kStrip];
 #pragma unroll
             for (int j = 0; j < kStrip; ++j)
-                hv[j] = __builtin_amdgcn_raw_buffer_load_b32(h1v.rs, (int)(hb + j * (hp - 4u)), 0, 0);
+                hv[j] = load_tab<TT>(h1v.rs, hb + j * (hp - hsz), 0);
             __builtin_amdgcn_sched_barrier(0);
             int m[kStrip], ia[kStrip];
             window_max<B, kStrip>(v, m, ia);
@@ -811,7 +827,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
 constexpr int kScanTile = 8;
 constexpr int kEmpty = -2147483647 - 1;  // no cell yet (below every V, -1 included)
 
-template <typename AT, int CAP>
+template <typename AT, int CAP, typename TT>
 __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     __shared__ int res_v[kWaves][kDCGeneric][64];
     __shared__ int res_i[kWaves][kDCGeneric][64];
@@ -835,7 +851,7 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
                                 kDCGeneric, D);
     int hv[kDCGeneric];
 #pragma unroll
-    for (int j = 0; j < kDCGeneric; ++j) hv[j] = load_h(a, xp, d0 + j);
+    for (int j = 0; j < kDCGeneric; ++j) hv[j] = load_h<TT>(a, xp, d0 + j);
     // The wave's windows, one per lane (lanes 0 .. kDCGeneric-1), read back as
     // scalars with readlane: no memory access inside the scans.
     int wlo = 0, whi = 0;
@@ -976,7 +992,7 @@ __global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
         if (r >= D || (unsigned)(x - mk.xlo) >= (unsigned)mk.xlen ||
             (unsigned)(x + d - mk.tlo) >= (unsigned)mk.tlen)
             continue;
-        take_best(best, pack_key(a.htab[(size_t)r * a.h_pitch + x], x, r, D), 0);
+        take_best(best, pack_key(static_cast<const int32_t*>(a.htab)[(size_t)r * a.h_pitch + x], x, r, D), 0);
     }
     finish(a, best, local);
 }
@@ -1311,10 +1327,24 @@ struct DpClass {
     int bound;  // fixed kernels: the template bound
     int dc;     // fixed kernels: displacements per thread
     bool a16;
+    bool narrow;  // uint16 tables (bands 0 .. k-2)
     bool operator==(const DpClass& o) const {
-        return kind == o.kind && bound == o.bound && dc == o.dc && a16 == o.a16;
+        return kind == o.kind && bound == o.bound && dc == o.dc && a16 == o.a16 &&
+               narrow == o.narrow;
     }
 };
+
+// Table of band i of an image (the last band is always int32: the DP reads
+// it as V_{k-1}).
+const void* band_table(const DpJobSpec& J, int i) {
+    const size_t band = (size_t)J.g.D * J.g.W;
+    if (i < J.tables.narrow) return J.tables.tab16 + (size_t)i * band;
+    return J.tables.wide + (size_t)(i - J.tables.narrow) * band;
+}
+
+const int32_t* last_table(const DpJobSpec& J) {
+    return static_cast<const int32_t*>(band_table(J, J.g.k - 1));
+}
 
 DpClass class_of(const DpJobSpec& j) {
     DpClass c;
@@ -1323,6 +1353,7 @@ DpClass class_of(const DpJobSpec& j) {
     c.bound = fixed ? j.plan.bound : 0;
     c.dc = fixed ? j.plan.dc : kDCGeneric;
     c.a16 = j.plan.a16;
+    c.narrow = j.tables.narrow > 0;
     if (!fixed) c.kind = (int)WindowKind::Generic;  // one scanning kernel for every other kind
     return c;
 }
@@ -1337,28 +1368,37 @@ int items_y_of(const Geometry& g, int dc) {
     return (chunks + kWaves - 1) / kWaves;
 }
 
-template <int B, typename AT, int CAP>
+template <int B, typename AT, int CAP, typename TT>
 void launch_fixed_b(int dc, hipStream_t s, const DpPack<CAP>& pk) {
     if (dc == 8)
-        hipLaunchKernelGGL((dp_step_fixed<B, 8, AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
+        hipLaunchKernelGGL((dp_step_fixed<B, 8, AT, CAP, TT>), dim3(pk.total), dim3(64 * kWaves), 0,
+                           s, pk);
     else
-        hipLaunchKernelGGL((dp_step_fixed<B, 16, AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
+        hipLaunchKernelGGL((dp_step_fixed<B, 16, AT, CAP, TT>), dim3(pk.total), dim3(64 * kWaves),
+                           0, s, pk);
 }
 
-template <typename AT, int CAP>
-hipError_t launch_step(const DpClass& c, hipStream_t s, const DpPack<CAP>& pk) {
+template <typename AT, int CAP, typename TT>
+hipError_t launch_step_t(const DpClass& c, hipStream_t s, const DpPack<CAP>& pk) {
     if (c.kind != (int)WindowKind::Fixed) {
-        hipLaunchKernelGGL((dp_step_generic<AT, CAP>), dim3(pk.total), dim3(64 * kWaves), 0, s, pk);
+        hipLaunchKernelGGL((dp_step_generic<AT, CAP, TT>), dim3(pk.total), dim3(64 * kWaves), 0, s,
+                           pk);
         return hipSuccess;
     }
 #define FHTP_B(BB) \
-    case BB: launch_fixed_b<BB, AT, CAP>(c.dc, s, pk); return hipSuccess;
+    case BB: launch_fixed_b<BB, AT, CAP, TT>(c.dc, s, pk); return hipSuccess;
     switch (c.bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
         FHTP_B(9) FHTP_B(10) FHTP_B(11) FHTP_B(12) FHTP_B(13) FHTP_B(14) FHTP_B(15) FHTP_B(16)
         default: return hipErrorInvalidValue;
     }
 #undef FHTP_B
+}
+
+template <typename AT, int CAP>
+hipError_t launch_step(const DpClass& c, hipStream_t s, const DpPack<CAP>& pk) {
+    return c.narrow ? launch_step_t<AT, CAP, uint16_t>(c, s, pk)
+                    : launch_step_t<AT, CAP, int32_t>(c, s, pk);
 }
 
 // Pin on V_{k-1} read from the table H_{k-1}: x_{k-1} is the column of the
@@ -1399,13 +1439,12 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
             const Geometry& g = J->g;
             if (g.k - 1 <= st) continue;
             const int i = g.k - 2 - st;  // band of this step
-            const size_t band = (size_t)g.D * g.W;
             const size_t plane = (size_t)g.D * g.pitch;
             DpJob a = base_job(*J);
-            a.vin = st == 0 ? J->tables + (size_t)(g.k - 1) * band
+            a.vin = st == 0 ? last_table(*J)
                             : J->buf.vplanes + (size_t)((i + 1) & 1) * plane;
             a.vin_pitch = st == 0 ? g.W : g.pitch;
-            a.htab = J->tables + (size_t)i * band;
+            a.htab = band_table(*J, i);
             const bool last = i == 0;
             // two planes in turn: step i only overwrites V_{i+2}, whose readers
             // (step i+1) finished with the previous launch
@@ -1429,12 +1468,12 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
     return hipSuccess;
 }
 
-template <typename AT, int CAP, bool PIN>
+template <typename AT, int CAP, bool PIN, typename TT>
 hipError_t launch_pair_p(int bound, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
-#define FHTP_B(BB)                                                                               \
-    case BB:                                                                                     \
-        hipLaunchKernelGGL((dp_pair_fixed<BB, AT, CAP, PIN>), dim3(grid), dim3(64 * kPairWaves), \
-                           0, s, pk);                                                            \
+#define FHTP_B(BB)                                                                         \
+    case BB:                                                                               \
+        hipLaunchKernelGGL((dp_pair_fixed<BB, AT, CAP, PIN, TT>), dim3(grid),              \
+                           dim3(64 * kPairWaves), 0, s, pk);                               \
         return hipSuccess;
     switch (bound) {
         FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
@@ -1445,14 +1484,22 @@ hipError_t launch_pair_p(int bound, hipStream_t s, int grid, const DpPairPack<CA
 }
 
 // Pinned packs exist only for single images (a batch job has no pin).
-template <typename AT, int CAP>
-hipError_t launch_pair(int bound, bool pinned, hipStream_t s, int grid, const DpPairPack<CAP>& pk) {
+template <typename AT, int CAP, typename TT>
+hipError_t launch_pair_t(int bound, bool pinned, hipStream_t s, int grid,
+                         const DpPairPack<CAP>& pk) {
     if constexpr (CAP == 1) {
-        if (pinned) return launch_pair_p<AT, CAP, true>(bound, s, grid, pk);
+        if (pinned) return launch_pair_p<AT, CAP, true, TT>(bound, s, grid, pk);
     } else {
         if (pinned) return hipErrorInvalidValue;
     }
-    return launch_pair_p<AT, CAP, false>(bound, s, grid, pk);
+    return launch_pair_p<AT, CAP, false, TT>(bound, s, grid, pk);
+}
+
+template <typename AT, int CAP>
+hipError_t launch_pair(int bound, bool pinned, bool narrow, hipStream_t s, int grid,
+                       const DpPairPack<CAP>& pk) {
+    return narrow ? launch_pair_t<AT, CAP, uint16_t>(bound, pinned, s, grid, pk)
+                  : launch_pair_t<AT, CAP, int32_t>(bound, pinned, s, grid, pk);
 }
 
 // Two steps per launch need the fixed window, the 8-displacement chunk (an
@@ -1492,7 +1539,7 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
     };
     auto input_of = [&](const DpJobSpec& J, int j, const int32_t*& vin, int& pitch) {
         if (j == 0) {
-            vin = J.tables + (size_t)(J.g.k - 1) * ((size_t)J.g.D * J.g.W);
+            vin = last_table(J);
             pitch = J.g.W;
         } else {
             vin = plane_of(J, j - 1);
@@ -1511,7 +1558,7 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
             input_of(*J, 0, a.vin, a.vin_pitch);
             first_step_pin(*J, a.vin_pin, a.vin_pin_x);
             a.out_pin_x = J->pin.j == i ? J->pin.x : -1;
-            a.htab = J->tables + (size_t)i * ((size_t)g.D * g.W);
+            a.htab = band_table(*J, i);
             a.vout = plane_of(*J, 0);
             a.aout = static_cast<AT*>(J->buf.a) + (size_t)(i - 1) * ((size_t)g.D * g.pitch);
             a.items_y = items_y_of(g, c.dc);
@@ -1538,7 +1585,6 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
             const int t = L - (Q - np);  // the image's pair index in this launch
             if (t < 0) continue;
             const int i = P - odd - 2 * t;  // phase-1 band; phase 2 makes band i-1
-            const size_t band = (size_t)g.D * g.W;
             const size_t plane = (size_t)g.D * g.pitch;
             AT* A = static_cast<AT*>(J->buf.a);
             DpPairJob a{};
@@ -1546,8 +1592,8 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
             if (odd + t == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);  // vin is H_{k-1}
             a.pin1_x = J->pin.j == i ? J->pin.x : -1;
             a.pin0_x = J->pin.j == i - 1 ? J->pin.x : -1;
-            a.h1 = J->tables + (size_t)i * band;
-            a.h0 = J->tables + (size_t)(i - 1) * band;
+            a.h1 = band_table(*J, i);
+            a.h0 = band_table(*J, i - 1);
             a.vout = plane_of(*J, odd + t);
             a.a1 = A + (size_t)(i - 1) * plane;  // A_{i+1}
             a.a0 = A + (size_t)(i - 2) * plane;  // A_i
@@ -1567,7 +1613,7 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
         bool pinned = false;
         for (int q = 0; q < cnt; ++q)
             pinned = pinned || pk.job[q].vin_pin != 0 || pk.job[q].pin1_x >= 0 || pk.job[q].pin0_x >= 0;
-        hipError_t e = launch_pair<AT, CAP>(jobs[0]->plan.bound, pinned, s, (int)total, pk);
+        hipError_t e = launch_pair<AT, CAP>(jobs[0]->plan.bound, pinned, c.narrow, s, (int)total, pk);
         if (e != hipSuccess) return e;
     }
     // last step of every image: V_1 (or the table H_1 when k = 2) to the keys
@@ -1582,7 +1628,7 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
         input_of(*J, m, a.vin, a.vin_pitch);
         if (m == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);  // k = 2: vin is H_1
         a.out_pin_x = J->pin.j == 0 ? J->pin.x : -1;
-        a.htab = J->tables;
+        a.htab = band_table(*J, 0);
         a.key = J->buf.key;
         a.succ = J->buf.succ;
         a.items_y = items_y_of(g, c.dc);
@@ -1652,7 +1698,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
         for (int q = 0; q < cnt; ++q) {
             const DpJobSpec& J = *single[q0 + q];
             DpJob a = base_job(J);
-            a.htab = J.tables;
+            a.htab = band_table(J, 0);  // k = 1: the only band is int32
             a.key = J.buf.key;
             a.succ = J.buf.succ;
             first_step_pin(J, a.vin_pin, a.vin_pin_x);
@@ -1740,7 +1786,7 @@ hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
+hipError_t launch_dp(const TableSet& tables, const Geometry& g, const DpPlan& plan,
                      const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream,
                      Pin pin) {
     DpJobSpec j{tables, g, plan, buf, score, xs, pin};

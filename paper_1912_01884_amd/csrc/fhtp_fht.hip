@@ -23,6 +23,7 @@
 // on 128-row sub-blocks, then a second kernel adds the sub-blocks along the
 // coarse levels of the recursion.
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "fhtp_internal.h"
@@ -204,10 +205,12 @@ __device__ __forceinline__ void fht_stages(int32_t (&v)[N], int32_t* lds, int co
 struct FhtJob {
     const void* img;  // first row of row block 0
     int32_t* out;     // tables [blocks][2n-1][W], or sub-block scratch
+    uint16_t* out16;  // narrow tables: bands 0 .. narrow-1 as [narrow][2n-1][W] uint16
     int w, W;         // image width, table width (w + band height)
     int T, tiles;     // columns produced per tile, tiles per row block
     int item0;        // first work item of this run in the launch
     int to_table;     // 1: band tables; 0: c-space sub-block scratch
+    int narrow;       // bands stored as uint16 (the rest, from band `narrow` on, go to out)
 };
 
 constexpr int kPack = 256;  // runs per launch (kernel arguments of up to 32 KB)
@@ -312,11 +315,29 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
     const int W = J.W;
     if (col >= J.T || it.c >= W) return;
     const unsigned int row_bytes = (unsigned int)W * 4u;
-    if (J.to_table) {
+    if (J.to_table && it.blk < J.narrow) {
+        // 16-bit table of a band whose line sums stay below 2^16
+        constexpr int D = 2 * N - 1;
+        const unsigned int row16 = (unsigned int)W * 2u;
+        const unsigned int voff = (unsigned int)(it.dir == 0 ? it.c : (W - 1 - it.c)) * 2u;
+        const __amdgpu_buffer_rsrc_t r =
+            make_rsrc(J.out16 + (size_t)it.blk * D * (size_t)W, (unsigned int)D * row16);
+        if (it.dir == 0) {
+#pragma unroll
+            for (int s = 0; s < N; ++s)
+                __builtin_amdgcn_raw_buffer_store_b16(
+                    (unsigned short)v[s], r, (int)voff, (int)((unsigned int)(N - 1 + s) * row16), 0);
+        } else {
+#pragma unroll
+            for (int s = 1; s < N; ++s)
+                __builtin_amdgcn_raw_buffer_store_b16(
+                    (unsigned short)v[s], r, (int)voff, (int)((unsigned int)(N - 1 - s) * row16), 0);
+        }
+    } else if (J.to_table) {
         constexpr int D = 2 * N - 1;
         const unsigned int voff = (unsigned int)(it.dir == 0 ? it.c : (W - 1 - it.c)) * 4u;
-        const __amdgpu_buffer_rsrc_t r =
-            make_rsrc(J.out + (size_t)it.blk * D * (size_t)W, (unsigned int)D * row_bytes);
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(
+            J.out + (size_t)(it.blk - J.narrow) * D * (size_t)W, (unsigned int)D * row_bytes);
         if (it.dir == 0) {
 #pragma unroll
             for (int s = 0; s < N; ++s)
@@ -431,9 +452,11 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
 // consecutive shifts; the offsets D_s(128 m) are uniform (scalar) per shift.
 struct CombineJob {
     const int32_t* sub;
-    int32_t* tables;
+    int32_t* tables;   // wide bands (from band `narrow` on), [.][2n-1][W] int32
+    uint16_t* tab16;   // narrow bands 0 .. narrow-1, [.][2n-1][W] uint16
     int p, W, k, tiles_x;
     int item0;
+    int narrow;
 };
 
 struct CombinePack {
@@ -485,7 +508,9 @@ __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
     if (c >= W) return;
     const size_t row = (size_t)W;
     const int32_t* base = J.sub + (size_t)band * M * 2 * (1 << kRegMaxP) * row;
-    int32_t* out = J.tables + (size_t)band * D * row;
+    const bool n16 = band < J.narrow;
+    int32_t* out = J.tables + (size_t)(band - J.narrow) * D * row;
+    uint16_t* out16 = J.tab16 + (size_t)band * D * row;
     const int xo = dir == 0 ? c : (W - 1 - c);
     // Every load of the workgroup's shifts first (all in flight together),
     // then the sums and the stores.
@@ -508,20 +533,38 @@ __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
         const int s = g * kShiftGroup + t;
         if (dir == 1 && s == 0) continue;
         const int r = dir == 0 ? (n - 1 + s) : (n - 1 - s);
-        out[(size_t)r * row + xo] = acc[t];
+        if (n16)
+            out16[(size_t)r * row + xo] = (uint16_t)acc[t];
+        else
+            out[(size_t)r * row + xo] = acc[t];
     }
 }
 
-int device_cus() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
+constexpr int kMaxDevices = 64;
+
+int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return 0;
     }
-    return cus;
+    return dev;
+}
+
+// Compute units of the current device, queried once per device.
+int device_cus() {
+    static std::atomic<int> cus[kMaxDevices];
+    const int dev = current_device();
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c <= 0) {
+            (void)hipGetLastError();
+            c = 256;
+        }
+        cus[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
 }
 
 // One register-kernel run to schedule (host side).
@@ -530,19 +573,25 @@ struct RegRun {
     int dtype, p;   // pixel type, log2 of the row-block height the kernel runs
     int w, W, blocks, to_table;
     int32_t* out;
+    uint16_t* out16;
+    int narrow;
 };
 
 template <int P, typename PixT, int CAP>
 hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
     using C = RegCfg<P>;
-    static int occupancy = 0;  // resident workgroups per CU for this instantiation
-    if (occupancy == 0) {
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fht_reg_kernel<P, PixT, CAP>, C::NT,
-                                                         0) != hipSuccess ||
-            occ <= 0)
-            occ = 1;
-        occupancy = occ;
+    // resident workgroups per CU for this instantiation, per device
+    static std::atomic<int> occ_of[kMaxDevices];
+    const int dev = current_device();
+    int occupancy = occ_of[dev].load(std::memory_order_relaxed);
+    if (occupancy <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occupancy, fht_reg_kernel<P, PixT, CAP>,
+                                                         C::NT, 0) != hipSuccess ||
+            occupancy <= 0) {
+            (void)hipGetLastError();
+            occupancy = 1;
+        }
+        occ_of[dev].store(occupancy, std::memory_order_relaxed);
     }
     const int Tmax = C::NC - (C::N - 1);
     FhtPack<CAP> pk{};
@@ -561,6 +610,8 @@ hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
         J.T = (r.W + tiles - 1) / tiles;
         J.item0 = (int)total;
         J.to_table = r.to_table;
+        J.out16 = r.out16;
+        J.narrow = r.narrow;
         total += (long long)tiles * r.blocks * C::NDIR;
         if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     }
@@ -617,11 +668,14 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
         r.dtype = J.dtype;
         r.w = g.w;
         r.W = g.W;
+        r.out16 = J.tables.narrow ? J.tables.tab16 : nullptr;
+        r.narrow = 0;
         if (g.p <= kRegMaxP) {
             r.p = g.p;
             r.blocks = g.k;
             r.to_table = 1;
-            r.out = J.tables;
+            r.out = J.tables.wide;
+            r.narrow = J.tables.narrow;
         } else {  // tall bands: 128-row sub-blocks first, then the coarse levels
             r.p = kRegMaxP;
             r.blocks = g.h >> kRegMaxP;
@@ -650,7 +704,9 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
         if (g.p <= kRegMaxP) continue;
         CombineJob c;
         c.sub = static_cast<const int32_t*>(jobs[q].scratch);
-        c.tables = jobs[q].tables;
+        c.tables = jobs[q].tables.wide;
+        c.tab16 = jobs[q].tables.tab16;
+        c.narrow = jobs[q].tables.narrow;
         c.p = g.p;
         c.W = g.W;
         c.k = g.k;
@@ -689,7 +745,7 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
     return hipSuccess;
 }
 
-hipError_t launch_fht(const void* img, int dtype, const Geometry& g, int32_t* tables,
+hipError_t launch_fht(const void* img, int dtype, const Geometry& g, const TableSet& tables,
                       void* scratch, hipStream_t stream) {
     FhtJobSpec j{img, dtype, g, tables, scratch};
     return launch_fht_jobs(&j, 1, stream);

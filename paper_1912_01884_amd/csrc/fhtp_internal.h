@@ -42,6 +42,23 @@ private:
 // Largest band height the register FHT kernel handles in one pass.
 constexpr int kRegMaxP = 7;
 
+// ---- band tables ------------------------------------------------------------
+// Where the band tables of one image live.  Wide: every band [k][D][W] int32
+// at `wide`.  Narrow (8-bit pixels and n <= 256, so every line sum is at most
+// 256 * 255 < 2^16): bands 0 .. narrow-1 as [narrow][D][W] uint16 at `tab16`,
+// the remaining bands (the last one, which the DP reads as V_{k-1}) as int32
+// at `wide`.  Narrow tables halve the table traffic of the FHT and the DP.
+struct TableSet {
+    int32_t* wide = nullptr;
+    uint16_t* tab16 = nullptr;
+    int narrow = 0;  // bands stored as uint16
+};
+
+// Whether a detection of this geometry and pixel type keeps narrow tables.
+inline bool narrow_tables_apply(const Geometry& g, int dtype) {
+    return dtype == 0 && g.n <= 256 && g.k >= 2;
+}
+
 // ---- band FHT -------------------------------------------------------------
 // Scratch needed by launch_fht (bytes, 0 when n <= 2^kRegMaxP).
 size_t fht_scratch_bytes(const Geometry& g);
@@ -51,13 +68,13 @@ struct FhtJobSpec {
     const void* img;
     int dtype;  // 0 = uint8, 1 = uint16
     Geometry g;
-    int32_t* tables;  // [k][D][W]
-    void* scratch;    // fht_scratch_bytes(g)
+    TableSet tables;
+    void* scratch;  // fht_scratch_bytes(g)
 };
 // Band tables of several images, launched in packs that share kernels.
 hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream);
-// Writes tables [k][D][W] int32.  dtype 0 = uint8, 1 = uint16.
-hipError_t launch_fht(const void* img, int dtype, const Geometry& g, int32_t* tables,
+// Writes the tables of one image.  dtype 0 = uint8, 1 = uint16.
+hipError_t launch_fht(const void* img, int dtype, const Geometry& g, const TableSet& tables,
                       void* scratch, hipStream_t stream);
 
 // ---- DP ---------------------------------------------------------------------
@@ -89,13 +106,13 @@ struct Pin {
 size_t dp_plane_bytes(const Geometry& g);
 size_t dp_backptr_bytes(const Geometry& g, bool a16);
 size_t dp_key_count(const Geometry& g);
-hipError_t launch_dp(const int32_t* tables, const Geometry& g, const DpPlan& plan,
+hipError_t launch_dp(const TableSet& tables, const Geometry& g, const DpPlan& plan,
                      const DpBuffers& buf, int32_t* score, int32_t* xs, hipStream_t stream,
                      Pin pin = Pin{});
 
 // One image's DP, argmax and walk.
 struct DpJobSpec {
-    const int32_t* tables;  // [k][D][W]
+    TableSet tables;
     Geometry g;
     DpPlan plan;
     DpBuffers buf;

@@ -122,6 +122,27 @@ def test_workspace_sizes_cover_the_buffers():
     assert fhtp.dp_workspace_bytes(2048, 1000, 4, b) >= 2 * 1023 * 1000 * 2
 
 
+def test_narrow_tables_shrink_the_workspace_exactly_where_they_are_exact():
+    """8-bit pixels with bands of at most 256 rows keep bands 0..k-2 as uint16
+    (a line sum is at most 256 * 255 < 2^16); the last band stays int32."""
+    b = fhtp.make_bend(4)
+    for h, w, k in [(1024, 1024, 16), (2048, 777, 8), (512, 300, 2), (256, 100, 1)]:
+        n = h // k
+        band = (2 * n - 1) * (w + n)
+        dp = fhtp.dp_workspace_bytes(h, w, k, b)
+        det8 = fhtp.detect_workspace_bytes(0, h, w, k, b)
+        det16 = fhtp.detect_workspace_bytes(1, h, w, k, b)
+        assert det16 >= dp + k * band * 4
+        narrow = k - 1 if k >= 2 else 0
+        assert det8 >= dp + narrow * band * 2 + (k - narrow) * band * 4
+        if k >= 2:
+            assert det8 < det16 - narrow * band * 2 + 4096  # only alignment on top
+    # 512-row bands of 8-bit pixels could reach 130,560: int32 tables
+    h, w, k = 2048, 500, 4
+    band = 1023 * (w + 512)
+    assert fhtp.detect_workspace_bytes(0, h, w, k, b) == fhtp.detect_workspace_bytes(1, h, w, k, b)
+
+
 def test_compute_calls_validate_before_launch():
     L = fhtp.lib()
     b = fhtp.make_bend(1)

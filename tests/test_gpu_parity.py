@@ -258,3 +258,34 @@ def test_detect_mixed_batch_images(dev, F, orc, j):
     sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, bend=s.bend)
     assert int(host(sc)[0]) == want_s
     assert host(xs).tolist() == want_x.tolist()
+
+
+NARROW_CASES = [
+    # (h, w, k, bend): 8-bit pixels, bands of at most 256 rows, so the
+    # detection keeps bands 0..k-2 as uint16 tables (line sums up to 65,280)
+    (512, 301, 2, 3),     # n = 256: one narrow band, the last one int32
+    (1024, 300, 4, 3),    # n = 256: two-pass FHT into narrow tables, one pair of steps
+    (2048, 260, 8, 1),    # n = 256, several pairs
+    (1024, 700, 8, 20),   # n = 128, scanned windows
+    (1024, 500, 16, 8),   # n = 64, single steps and pairs
+]
+
+
+@pytest.mark.parametrize("h,w,k,bend", NARROW_CASES,
+                         ids=[f"{c[0]}x{c[1]}k{c[2]}b{c[3]}" for c in NARROW_CASES])
+def test_narrow_tables_at_the_bound(dev, F, orc, h, w, k, bend):
+    """Near-saturated 8-bit images: every table value of a narrow band is close
+    to (or, on the all-255 columns, exactly) its uint16 ceiling of n * 255."""
+    rng = np.random.default_rng([191201884, 77, h, w, k])
+    img = rng.integers(200, 256, size=(h, w)).astype(np.uint8)
+    img[:, ::7] = 255
+    img[rng.random((h, w)) < 0.01] = 0
+    announce(f"narrow tables {h}x{w} k={k} bend={bend}")
+    sc, xs = F.detect_polyline(to_device(img, dev), k, bend=bend)
+    want_s, want_x = orc.detect_polyline(img, k, bend=bend)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+    full = np.full((h, w), 255, np.uint8)
+    sc, xs = F.detect_polyline(to_device(full, dev), k, bend=bend)
+    assert int(host(sc)[0]) == 255 * h
+    assert not host(xs).any()
