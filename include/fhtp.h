@@ -145,6 +145,27 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
                          void* ws, size_t ws_bytes, int32_t* score, int32_t* xs, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * fhtp_detect_polyline without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It computes exactly what
+ * fhtp_detect_polyline computes (same arguments, same results, same errors)
+ * but keeps its band tables, value planes, back-pointers and keys in a
+ * device array built into the library: fhtp_noalloc_scratch_bytes() bytes
+ * (64 MiB) per GPU, held from the library's first use of that GPU until the
+ * process ends.  The call allocates and frees nothing.
+ *
+ * Limit: requests whose fhtp_detect_workspace_bytes exceeds the scratch size
+ * (for example a 4096 x 4096 image) return FHTP_ERR_WORKSPACE and enqueue
+ * nothing.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap in time on one GPU (different streams,
+ * or threads without ordering) race and give undefined results; order them
+ * on one stream.  img, score and xs are caller-owned device memory as above.
+ * ------------------------------------------------------------------------- */
+size_t fhtp_noalloc_scratch_bytes(void);
+int fhtp_detect_polyline_noalloc(const void* img, fhtp_dtype dtype, int h, int w, int k,
+                                 fhtp_bend bend, int32_t* score, int32_t* xs, void* stream);
+
+/* ---------------------------------------------------------------------------
  * The detector with its optional steps (all off when opt is NULL or zeroed
  * with pin_boundary = -1), applied in this order:
  *

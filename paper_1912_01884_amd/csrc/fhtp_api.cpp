@@ -297,6 +297,46 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
 
 namespace {
 
+// ---- the allocation-free entry point -----------------------------------------
+//
+// Device scratch for fhtp_detect_polyline_noalloc: one array per GPU, part of
+// the library's code object, held until the process ends.  Host code never
+// uses its name as an address: the first call on a device takes the device
+// address with hipGetSymbolAddress (that device current) and keeps it.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxScratchDevices = 64;
+
+struct ScratchSlot {
+    std::once_flag once;
+    void* ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+
+ScratchSlot g_scratch[kMaxScratchDevices];
+
+// Device address of the current device's scratch array.
+int scratch_of_current_device(void** out) {
+    int dev = 0;
+    int rc = hip_status(hipGetDevice(&dev), "detect_polyline_noalloc/device");
+    if (rc != FHTP_OK) return rc;
+    if (dev < 0 || dev >= kMaxScratchDevices) return FHTP_ERR_UNSUPPORTED;
+    ScratchSlot& slot = g_scratch[dev];
+    std::call_once(slot.once, [&] {
+        slot.err = hipGetSymbolAddress(&slot.ptr, HIP_SYMBOL(scratch));
+        if (slot.err != hipSuccess) {
+            (void)hipGetLastError();
+            slot.ptr = nullptr;
+        }
+    });
+    if (slot.err != hipSuccess || !slot.ptr)
+        return hip_status(slot.err != hipSuccess ? slot.err : hipErrorInvalidSymbol,
+                          "detect_polyline_noalloc/scratch address");
+    *out = slot.ptr;
+    return FHTP_OK;
+}
+
 constexpr int kMaxSmoothRadius = 7;
 
 // Validated extended request: the detection image's geometry and where the
@@ -345,6 +385,33 @@ int fhtp_prepare_image(const void* img, fhtp_dtype dtype, int h, int w, int smoo
     return hip_status(fhtp::launch_prep(img, (int)dtype, h, w, smooth_radius, horizontal, out,
                                         static_cast<hipStream_t>(stream)),
                       "prepare_image");
+}
+
+size_t fhtp_noalloc_scratch_bytes(void) { return kNoAllocBytes; }
+
+int fhtp_detect_polyline_noalloc(const void* img, fhtp_dtype dtype, int h, int w, int k,
+                                 fhtp_bend bend, int32_t* score, int32_t* xs, void* stream) {
+    if (!img || !score || !xs) return FHTP_ERR_NULL;
+    fhtp::Geometry g;
+    fhtp::DpPlan pl;
+    int rc = shape(h, w, k, &g);
+    if (rc == FHTP_OK) rc = pixels(dtype, h);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc != FHTP_OK) return rc;
+    const DetectLayout L = detect_layout(g, pl, dtype);
+    if (L.dp.end > kNoAllocBytes) return FHTP_ERR_WORKSPACE;
+    void* ws = nullptr;
+    rc = scratch_of_current_device(&ws);
+    if (rc != FHTP_OK) return rc;
+    char* base = static_cast<char*>(ws);
+    const fhtp::TableSet tables = table_set(base, L);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s),
+                    "detect_polyline_noalloc/fht");
+    if (rc != FHTP_OK) return rc;
+    return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(base, L.dp), score, xs, s),
+                      "detect_polyline_noalloc/dp");
 }
 
 int fhtp_detect_ex_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,

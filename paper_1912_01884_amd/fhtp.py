@@ -36,7 +36,8 @@ EXPORTED = (
     "fhtp_detect_workspace_bytes", "fhtp_detect_polyline", "fhtp_batch_workspace_bytes",
     "fhtp_detect_batch", "fhtp_detect_ex_workspace_bytes", "fhtp_detect_polyline_ex",
     "fhtp_prepare_image", "fhtp_plan_create", "fhtp_plan_capture", "fhtp_plan_launch",
-    "fhtp_plan_destroy", "fhtp_timing_start", "fhtp_timing_stop",
+    "fhtp_plan_destroy", "fhtp_timing_start", "fhtp_timing_stop", "fhtp_noalloc_scratch_bytes",
+    "fhtp_detect_polyline_noalloc",
 )
 
 
@@ -125,10 +126,13 @@ def lib() -> C.CDLL:
     L.fhtp_plan_launch.argtypes = [vp, vp]
     L.fhtp_plan_destroy.argtypes = [vp]
     L.fhtp_timing_start.argtypes = []
+    L.fhtp_noalloc_scratch_bytes.argtypes = []
+    L.fhtp_detect_polyline_noalloc.argtypes = [vp, i32, i32, i32, i32, Bend, vp, vp, vp]
     L.fhtp_timing_stop.argtypes = [C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
     for name in EXPORTED:
         if name not in ("fhtp_strerror", "fhtp_last_error_detail", "fhtp_version"):
             getattr(L, name).restype = C.c_int
+    L.fhtp_noalloc_scratch_bytes.restype = C.c_size_t
     _lib = L
     return L
 
@@ -306,6 +310,30 @@ def detect_polyline(img, k: int, bend: Optional[int] = None, gamma: Optional[flo
         rc = lib().fhtp_detect_polyline(img.data_ptr(), dt, h, w, k, b, _ptr(ws_t), ws_n,
                                         score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
     _check(rc, "detect_polyline")
+    return score, xs
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the scratch array fhtp_detect_polyline_noalloc uses on each GPU."""
+    return int(lib().fhtp_noalloc_scratch_bytes())
+
+
+def detect_polyline_noalloc(img, k: int, bend: Optional[int] = None,
+                            gamma: Optional[float] = None, score=None, xs=None, stream=None):
+    """detect_polyline through the entry point that allocates no device memory."""
+    torch = _torch()
+    _require_device(img, "img")
+    h, w = img.shape
+    b = make_bend(bend, gamma)
+    with _on_stream(stream):
+        if score is None:
+            score = torch.empty(1, dtype=torch.int32, device=img.device)
+        if xs is None:
+            xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
+        rc = lib().fhtp_detect_polyline_noalloc(img.data_ptr(), _dtype_code(img), h, w, k, b,
+                                                score.data_ptr(), xs.data_ptr(),
+                                                _stream_ptr(stream))
+    _check(rc, "detect_polyline_noalloc")
     return score, xs
 
 

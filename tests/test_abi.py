@@ -279,3 +279,20 @@ def test_timing_hook_is_host_only_when_nothing_ran():
     L = fhtp.lib()
     assert L.fhtp_timing_stop(None, 4, None) == fhtp.ERR_NULL
 
+
+def test_noalloc_validates_before_launch():
+    """Host-side refusals of the allocation-free entry point (nothing reaches the GPU)."""
+    import ctypes as C
+    from paper_1912_01884_amd import fhtp
+    L = fhtp.lib()
+    b = fhtp.make_bend(8)
+    p = C.c_void_p(256)  # never dereferenced: every call below is refused on the host
+    assert fhtp.noalloc_scratch_bytes() == 64 << 20
+    assert L.fhtp_detect_polyline_noalloc(None, 0, 64, 64, 4, b, p, p, None) == fhtp.ERR_NULL
+    assert L.fhtp_detect_polyline_noalloc(p, 0, 64, 64, 3, b, p, p, None) == fhtp.ERR_DIMS
+    assert L.fhtp_detect_polyline_noalloc(p, 5, 64, 64, 4, b, p, p, None) == fhtp.ERR_DTYPE
+    assert L.fhtp_detect_polyline_noalloc(p, 0, 64, 64, 4, fhtp.Bend(0, -1, 0.0), p, p,
+                                          None) == fhtp.ERR_BEND
+    # larger than the built-in array
+    assert L.fhtp_detect_polyline_noalloc(p, 1, 4096, 4096, 32, b, p, p, None) == \
+        fhtp.ERR_WORKSPACE
