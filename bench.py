@@ -37,8 +37,9 @@ TRAFFIC = {}
 def byte_model(h, w, k, bpp):
     """Algorithmic HBM bytes of one detection with materialised band tables.
 
-    The image is read once, the tables [k][2n-1][w+n] int32 are written once
-    by the FHT and read once by the DP, and one back-pointer per DP cell and
+    The image is read once, the tables [k][2n-1][w+n] are written once by the
+    FHT and read once by the DP (int32 cells, or uint16 where 8-bit pixels
+    keep every line sum below 2^16), and one back-pointer per DP cell and
     band boundary is written ((k-1)(2n-1)w of them, one byte each while 2n-1
     fits a byte, else two).  The DP's value planes are not counted: the
     dataflow keeps them in cache, and their traffic is reported apart.
@@ -47,12 +48,16 @@ def byte_model(h, w, k, bpp):
     D, W = 2 * n - 1, w + n
     ab = 1 if D <= 256 else 2
     image = h * w * bpp
-    tables = 4 * k * D * W
+    # 8-bit pixels and bands of at most 256 rows: bands 0..k-2 are stored as
+    # uint16 (every line sum fits), the last one as int32
+    narrow = k - 1 if (bpp == 1 and n <= 256 and k >= 2) else 0
+    tb = 2 if narrow else 4  # bytes of a table cell of the bands the DP steps read
+    tables = D * W * (2 * narrow + 4 * (k - narrow))
     backptr = max(k - 1, 0) * D * w * ab
     return {"image": image, "tables_write": tables, "tables_read": tables, "backptr": backptr,
             "total": image + 2 * tables + backptr, "fht_kernel": image + tables,
-            "dp_per_band": 4 * D * W + D * w * ab, "table_read_per_band": 4 * D * W,
-            "backptr_per_band": D * w * ab, "v_plane": 4 * D * w}
+            "dp_per_band": tb * D * W + D * w * ab, "table_read_per_band": tb * D * W,
+            "backptr_per_band": D * w * ab, "v_plane": 4 * D * w, "table_cell_bytes": tb}
 
 
 def time_events(fn, reps, stream):
@@ -150,21 +155,30 @@ def single_detections(step, stream, reps, flush=None):
     return {"median": round(out[len(out) // 2], 4), "min": round(out[0], 4), "reps": reps}
 
 
-def mixed_batch(n_images, reps, dev, stream):
+def mixed_batch(n_images, reps, dev, stream, tune=True, plan_out=None):
     """The mixed-size workload: images/s one detection at a time vs one batched call.
 
     Both paths get prebuilt arguments and preallocated workspaces, so the
     comparison is between the library's two entry points, not Python overhead.
+    With `tune`, the autotuner first picks the launch shapes for this workload
+    (both paths then run with them).
     """
     import ctypes as C
 
     import torch
 
     import synth
-    from paper_1912_01884_amd import fhtp
+    from paper_1912_01884_amd import autotune, fhtp
 
     batch = synth.make_mixed_batch(n_images)
     imgs = [torch.from_numpy(s.image).to(dev) for s in batch]
+    tuning = None
+    if tune:
+        res = autotune.tune(imgs, [s.k for s in batch], bends=[s.bend for s in batch], reps=3,
+                            stream=stream)
+        tuning = res.as_dict()
+        if plan_out:
+            autotune.save(res, plan_out, workload=f"mixed-size batch of {n_images} images")
     jobs, keep = fhtp.make_jobs(imgs, [s.k for s in batch], bends=[s.bend for s in batch])
     L = fhtp.lib()
     sptr = int(stream.cuda_stream)
@@ -218,7 +232,8 @@ def mixed_batch(n_images, reps, dev, stream):
             "graph_ms": round(ms_graph, 3), "graph_identical_to_batched": same,
             "speedup": round(ms_plain / ms_batch, 2),
             "graph_speedup": round(ms_plain / ms_graph, 2),
-            "batched_mpix_per_s": round(mpix / (best * 1e-3), 1)}
+            "batched_mpix_per_s": round(mpix / (best * 1e-3), 1),
+            "tuning": tuning}
 
 
 def serving(dev, rates, count, streams=4, max_batch=256):
@@ -488,6 +503,10 @@ def main():
                     help="requests per arrival rate in the serving run (0 skips it)")
     ap.add_argument("--serve-rates", default="200,1000,5000,inf",
                     help="Poisson arrival rates (requests/s) of the serving run; inf = all at once")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="run with the library's default launch shapes (no autotuning)")
+    ap.add_argument("--plan-out", default=None,
+                    help="save the mixed workload's tuned rules to this JSON file")
     ap.add_argument("--probe", action="store_true",
                     help="run the short counter-calibration program instead of the benchmark")
     ap.add_argument("--summarize-trace", metavar="DIR",
@@ -531,6 +550,14 @@ def main():
 
     def step():
         fhtp.detect_polyline(img, k, bend=B, ws=ws, score=score, xs=xs, stream=stream)
+
+    # Launch shapes for this workload, picked by the autotuner before the
+    # timed region (results are the same under every candidate).
+    from paper_1912_01884_amd import autotune
+    tuning = None
+    if not args.no_tune:
+        tuning = autotune.tune([img], [k], bends=[B], reps=max(5, args.steps // 2),
+                               stream=stream).as_dict()
 
     for _ in range(args.warmup):
         step()
@@ -630,6 +657,7 @@ def main():
         "model_bytes": {q: model[q] for q in ("image", "tables_write", "tables_read", "backptr",
                                               "total")},
         "launch": launch,
+        "tuning": tuning,
         "eager_ms_per_step": round(ms_eager, 4),
         "graph_ms_per_step": round(ms_graph, 4),
         "phase_ms": {"fht_bands": round(ms_fht, 4), "polyline_dp": round(ms_dp, 4)},
@@ -680,7 +708,8 @@ def main():
         }
         del wsp
     if args.batch_images > 0:
-        line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream)
+        line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream,
+                                          tune=not args.no_tune, plan_out=args.plan_out)
     if args.serve_requests > 0:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
         line["serving"] = serving(dev, rates, args.serve_requests)

@@ -287,6 +287,48 @@ int fhtp_plan_launch(fhtp_plan plan, void* stream);
 int fhtp_plan_destroy(fhtp_plan plan);
 
 /* ---------------------------------------------------------------------------
+ * Tuning rules: launch shapes chosen per kind of request (not part of the
+ * method; no rule changes any result, only how the work is cut into
+ * launches and workgroups).
+ *
+ * A rule covers requests by pixel type (-1: any), band height 2^log2n (-1:
+ * any), image width in [w_min, w_max] and window kind (0: the fixed window of
+ * a mode-0 bound of at most 16 shifts; 1: scanned windows, i.e. larger
+ * bounds, the angle form and the unbounded bend; -1: any).  For the requests
+ * it covers it sets:
+ *   dc:       displacements per thread of one-step fixed-window launches, 8 or
+ *             16 (0: the library's choice by grid size);
+ *   pairs:    1: two DP steps per launch where the window allows it (needs
+ *             dc 8), 0: one step per launch;
+ *   stripe:   column tiles per stripe of the two-step kernel's workgroup
+ *             order, 1..64 (0: 16);
+ *   fht_grid: 0: the FHT's resident grid loops over the work items; 1: one
+ *             workgroup per work item.
+ * fhtp_tune_set replaces the process-wide rule list (count 0 clears it); at
+ *   most 1024 rules, each validated (FHTP_ERR_OPTION, nothing changed, if one
+ *   is out of range).  Requests are matched against the rules, first match
+ *   wins, when they are planned: every detect call, batch call and plan
+ *   capture (a captured plan keeps the shapes it was recorded with).  Requests
+ *   without a pixel type (fhtp_polyline_dp) match only rules with dtype -1.
+ * fhtp_tune_get copies up to `cap` rules to `out` (host memory) and the rule
+ *   count to *count.
+ * Host calls, safe to call from any thread.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t dtype;
+    int32_t log2n;
+    int32_t w_min, w_max;
+    int32_t window;
+    int32_t dc;
+    int32_t pairs;
+    int32_t stripe;
+    int32_t fht_grid;
+} fhtp_tune_rule;
+
+int fhtp_tune_set(const fhtp_tune_rule* rules, int count);
+int fhtp_tune_get(fhtp_tune_rule* out, int cap, int* count);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing, for benchmarks and tuning (not part of the method).
  *
  * fhtp_timing_start: clears earlier records and turns timing on for the

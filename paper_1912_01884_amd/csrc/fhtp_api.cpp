@@ -66,9 +66,47 @@ int dp_chunk(const fhtp::Geometry& g) {
     return threads16 < 256LL * 4 * 64 * 2 ? 8 : 16;
 }
 
-int plan(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
+// ---- tuning rules (fhtp_tune_set) ----------------------------------------------
+//
+// Launch-shape choices that never change a result: the first rule matching a
+// request overrides the defaults below.  Held process-wide; consulted when a
+// request is planned (plans keep what their capture saw).
+constexpr int kMaxTuneRules = 1024;
+std::mutex g_tune_mu;
+std::vector<fhtp_tune_rule> g_tune;
+
+bool rule_valid(const fhtp_tune_rule& r) {
+    return r.dtype >= -1 && r.dtype <= 1 && r.log2n >= -1 && r.log2n <= 10 && r.w_min >= 0 &&
+           r.w_min <= r.w_max && r.window >= -1 && r.window <= 1 &&
+           (r.dc == 0 || r.dc == 8 || r.dc == 16) && (r.pairs == 0 || r.pairs == 1) &&
+           r.stripe >= 0 && r.stripe <= 64 && (r.fht_grid == 0 || r.fht_grid == 1);
+}
+
+// Knobs for a planned request: dtype -1 when the pixel type is not part of
+// the request (fhtp_polyline_dp), then only rules for any pixel type match.
+void apply_tuning(const fhtp::Geometry& g, int dtype, fhtp::DpPlan* pl) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const int window = pl->kind == fhtp::WindowKind::Fixed ? 0 : 1;
+    for (const fhtp_tune_rule& r : g_tune) {
+        if (r.dtype != -1 && r.dtype != dtype) continue;
+        if (r.log2n != -1 && r.log2n != g.p) continue;
+        if (g.w < r.w_min || g.w > r.w_max) continue;
+        if (r.window != -1 && r.window != window) continue;
+        if (r.dc) pl->dc = r.dc;
+        pl->pairs = r.pairs != 0;
+        pl->stripe = r.stripe ? r.stripe : 16;
+        pl->fht_grid = r.fht_grid;
+        return;
+    }
+}
+
+// The DP's window kind for a bend restriction (Section 2.3), before tuning.
+int plan_window(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
     pl->a16 = g.D > 256;
     pl->dc = dp_chunk(g);
+    pl->pairs = true;
+    pl->stripe = 16;
+    pl->fht_grid = 0;
     pl->bound = 0;
     pl->tan_gamma = 0.0;
     if (b.mode == 0) {
@@ -93,6 +131,12 @@ int plan(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
         return FHTP_OK;
     }
     return FHTP_ERR_BEND;
+}
+
+int plan(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl, int dtype = -1) {
+    const int rc = plan_window(g, b, pl);
+    if (rc == FHTP_OK) apply_tuning(g, dtype, pl);
+    return rc;
 }
 
 struct DpLayout {
@@ -259,6 +303,24 @@ int fhtp_polyline_dp(const int32_t* tables, int h, int w, int k, fhtp_bend bend,
                       "polyline_dp");
 }
 
+int fhtp_tune_set(const fhtp_tune_rule* rules, int count) {
+    if (count < 0 || count > kMaxTuneRules) return FHTP_ERR_OPTION;
+    if (count > 0 && !rules) return FHTP_ERR_NULL;
+    for (int q = 0; q < count; ++q)
+        if (!rule_valid(rules[q])) return FHTP_ERR_OPTION;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.assign(rules, rules + count);
+    return FHTP_OK;
+}
+
+int fhtp_tune_get(fhtp_tune_rule* out, int cap, int* count) {
+    if (!count || (cap > 0 && !out)) return FHTP_ERR_NULL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    *count = (int)g_tune.size();
+    for (int q = 0; q < cap && q < (int)g_tune.size(); ++q) out[q] = g_tune[q];
+    return FHTP_OK;
+}
+
 int fhtp_detect_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend,
                                 size_t* bytes) {
     if (!bytes) return FHTP_ERR_NULL;
@@ -266,7 +328,7 @@ int fhtp_detect_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, fhtp_bend
     fhtp::DpPlan pl;
     int rc = shape(h, w, k, &g);
     if (rc == FHTP_OK) rc = pixels(dtype, h);
-    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl, (int)dtype);
     if (rc != FHTP_OK) return rc;
     *bytes = detect_layout(g, pl, dtype).dp.end;
     return FHTP_OK;
@@ -279,7 +341,7 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
     fhtp::DpPlan pl;
     int rc = shape(h, w, k, &g);
     if (rc == FHTP_OK) rc = pixels(dtype, h);
-    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl, (int)dtype);
     if (rc != FHTP_OK) return rc;
     const DetectLayout L = detect_layout(g, pl, dtype);
     rc = check_ws(ws, ws_bytes, L.dp.end);
@@ -288,7 +350,7 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
     const fhtp::TableSet tables = table_set(base, L);
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s),
+    rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s, pl.fht_grid),
                     "detect_polyline/fht");
     if (rc != FHTP_OK) return rc;
     return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(base, L.dp), score, xs, s),
@@ -359,7 +421,7 @@ int plan_ex(fhtp_dtype dtype, int h, int w, int k, fhtp_bend bend, const fhtp_op
     const int hh = o.horizontal ? w : h, ww = o.horizontal ? h : w;
     int rc = shape(hh, ww, k, &e->g);
     if (rc == FHTP_OK) rc = pixels(dtype, hh);
-    if (rc == FHTP_OK) rc = plan(e->g, bend, &e->pl);
+    if (rc == FHTP_OK) rc = plan(e->g, bend, &e->pl, (int)dtype);
     if (rc != FHTP_OK) return rc;
     if (o.pin_boundary < -1 || o.pin_boundary > k) return FHTP_ERR_POINT;
     if (o.pin_boundary >= 0 && (o.pin_pos < 0 || o.pin_pos >= ww)) return FHTP_ERR_POINT;
@@ -396,7 +458,7 @@ int fhtp_detect_polyline_noalloc(const void* img, fhtp_dtype dtype, int h, int w
     fhtp::DpPlan pl;
     int rc = shape(h, w, k, &g);
     if (rc == FHTP_OK) rc = pixels(dtype, h);
-    if (rc == FHTP_OK) rc = plan(g, bend, &pl);
+    if (rc == FHTP_OK) rc = plan(g, bend, &pl, (int)dtype);
     if (rc != FHTP_OK) return rc;
     const DetectLayout L = detect_layout(g, pl, dtype);
     if (L.dp.end > kNoAllocBytes) return FHTP_ERR_WORKSPACE;
@@ -407,7 +469,7 @@ int fhtp_detect_polyline_noalloc(const void* img, fhtp_dtype dtype, int h, int w
     const fhtp::TableSet tables = table_set(base, L);
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s),
+    rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s, pl.fht_grid),
                     "detect_polyline_noalloc/fht");
     if (rc != FHTP_OK) return rc;
     return hip_status(fhtp::launch_dp(tables, g, pl, dp_buffers(base, L.dp), score, xs, s),
@@ -446,7 +508,8 @@ int fhtp_detect_polyline_ex(const void* img, fhtp_dtype dtype, int h, int w, int
         base += e.prep_bytes;
     }
     const fhtp::TableSet tables = table_set(base, e.L);
-    rc = hip_status(fhtp::launch_fht(det, (int)dtype, e.g, tables, base + e.L.scratch, s),
+    rc = hip_status(fhtp::launch_fht(det, (int)dtype, e.g, tables, base + e.L.scratch, s,
+                                     e.pl.fht_grid),
                     "detect_polyline_ex/fht");
     if (rc != FHTP_OK) return rc;
     return hip_status(fhtp::launch_dp(tables, e.g, e.pl, dp_buffers(base, e.L.dp), score, xs, s,
@@ -476,7 +539,7 @@ int plan_batch(const fhtp_job* jobs, int count, std::vector<BatchEntry>* out, si
         if (!J.img || !J.score || !J.xs) return FHTP_ERR_NULL;
         int rc = shape(J.h, J.w, J.k, &e.g);
         if (rc == FHTP_OK) rc = pixels((fhtp_dtype)J.dtype, J.h);
-        if (rc == FHTP_OK) rc = plan(e.g, J.bend, &e.pl);
+        if (rc == FHTP_OK) rc = plan(e.g, J.bend, &e.pl, J.dtype);
         if (rc != FHTP_OK) {
             char buf[64];
             std::snprintf(buf, sizeof(buf), "job %d", q);
@@ -610,7 +673,8 @@ int detect_batch_on(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, 
         const BatchEntry& e = plan_v[q];
         char* base = static_cast<char*>(ws) + e.offset;
         const fhtp::TableSet tables = table_set(base, e.L);
-        fj[q] = fhtp::FhtJobSpec{jobs[q].img, (int)jobs[q].dtype, e.g, tables, base + e.L.scratch};
+        fj[q] = fhtp::FhtJobSpec{jobs[q].img, (int)jobs[q].dtype, e.g, tables, base + e.L.scratch,
+                                 e.pl.fht_grid};
         dj[q] = fhtp::DpJobSpec{tables, e.g, e.pl, dp_buffers(base, e.L.dp), jobs[q].score,
                                 jobs[q].xs};
     }

@@ -631,9 +631,8 @@ template <int CAP>
 struct DpPairPack {
     DpPairJob job[CAP];
     int count;
+    int stripe;  // column tiles per stripe of the item order (tuned; 16 by default)
 };
-
-constexpr int kStripeTiles = 16;  // column tiles per stripe of the pair kernel's item order
 
 // Masks: a thread's loads of V_{i+2} are consecutive rows of one column, so
 // the valid ones form a range of the row index; table loads are not masked
@@ -658,7 +657,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     __shared__ AT nxt[NS * kStrip][LWP];   // row of that cell's window maximum (its choice)
 
     // Workgroup b runs on XCD b % 8.  Each XCD gets a contiguous run of items
-    // instead, an image's items in stripes of kStripeTiles column tiles (every
+    // instead, an image's items in stripes of pk.stripe column tiles (every
     // row group of a stripe before the next stripe), so that the overlapping
     // reads of neighbouring workgroups (the widened rows, a strip's extra
     // columns, the diagonal shift between row groups) meet in one L2.
@@ -680,11 +679,12 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     int bx, by;
     {
         const int local = CAP > 1 ? it - a.item0 : it;  // one image: item0 is 0
-        const int per_stripe = kStripeTiles * a.items_y;
+        const int stripe = pk.stripe;
+        const int per_stripe = stripe * a.items_y;
         const int st = local / per_stripe, loc = local - st * per_stripe;
-        const int sw = min(kStripeTiles, a.items_x - st * kStripeTiles);
+        const int sw = min(stripe, a.items_x - st * stripe);
         by = loc / sw;
-        bx = st * kStripeTiles + (loc - by * sw);
+        bx = st * stripe + (loc - by * sw);
     }
     const int X0 = bx * 64;
     const int r0 = by * kPairRows;  // table row of the first displacement of step i
@@ -1328,9 +1328,11 @@ struct DpClass {
     int dc;     // fixed kernels: displacements per thread
     bool a16;
     bool narrow;  // uint16 tables (bands 0 .. k-2)
+    bool pairs;   // two steps per launch allowed (tuning)
+    int stripe;   // item-order stripe of the two-step kernel (tuning)
     bool operator==(const DpClass& o) const {
         return kind == o.kind && bound == o.bound && dc == o.dc && a16 == o.a16 &&
-               narrow == o.narrow;
+               narrow == o.narrow && pairs == o.pairs && stripe == o.stripe;
     }
 };
 
@@ -1354,6 +1356,8 @@ DpClass class_of(const DpJobSpec& j) {
     c.dc = fixed ? j.plan.dc : kDCGeneric;
     c.a16 = j.plan.a16;
     c.narrow = j.tables.narrow > 0;
+    c.pairs = j.plan.pairs;
+    c.stripe = j.plan.stripe;
     if (!fixed) c.kind = (int)WindowKind::Generic;  // one scanning kernel for every other kind
     return c;
 }
@@ -1509,8 +1513,8 @@ bool pairs_apply(const DpJobSpec& J) {
     const Geometry& g = J.g;
     const long long rows = kPairRows + 4LL * kMaxFixedB + kStrip;  // the widest view
     const long long pitch = std::max(g.W, g.pitch);
-    return J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC && g.k >= 2 &&
-           rows * pitch * 4 < 0x7fffffffLL;
+    return J.plan.pairs && J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC &&
+           g.k >= 2 && rows * pitch * 4 < 0x7fffffffLL;
 }
 
 // Steps of a pack of images of one class with bands k-2 .. 1 taken two per
@@ -1610,6 +1614,7 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
             pk.job[cnt++] = a;
         }
         pk.count = cnt;
+        pk.stripe = std::max(1, c.stripe);
         bool pinned = false;
         for (int q = 0; q < cnt; ++q)
             pinned = pinned || pk.job[q].vin_pin != 0 || pk.job[q].pin1_x >= 0 || pk.job[q].pin0_x >= 0;
@@ -1756,7 +1761,9 @@ size_t dp_key_count(const Geometry& g) {
 }
 
 size_t dp_backptr_bytes(const Geometry& g, bool a16) {
-    // Planes for A_2 .. A_{k-1}; A_1 is re-derived from V_1 during the walk.
+    // Planes for A_2 .. A_{k-1}; there is no A_1 plane: the last step records,
+    // with each workgroup's key, the successor of that cell (its row in the
+    // succ buffer), and the walk starts from it.
     const size_t planes = g.k > 2 ? (size_t)(g.k - 2) : 1;
     return planes * g.D * g.pitch * (a16 ? 2 : 1);
 }

@@ -575,6 +575,7 @@ struct RegRun {
     int32_t* out;
     uint16_t* out16;
     int narrow;
+    int grid_mode;  // 0: resident grid; 1: one workgroup per item
 };
 
 template <int P, typename PixT, int CAP>
@@ -618,7 +619,9 @@ hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
     pk.count = count;
     pk.total = (int)total;
     if (total == 0) return hipSuccess;
-    const long long slots = (long long)occupancy * device_cus();
+    // Resident grid (as many workgroups as the chip keeps, looping over the
+    // items) unless the pack asks for one workgroup per item.
+    const long long slots = runs[0].grid_mode ? total : (long long)occupancy * device_cus();
     const int grid = (int)(total < slots ? total : slots);
     {
         TimedLaunch tl("fht_reg_kernel", stream);
@@ -670,6 +673,7 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
         r.W = g.W;
         r.out16 = J.tables.narrow ? J.tables.tab16 : nullptr;
         r.narrow = 0;
+        r.grid_mode = J.grid_mode;
         if (g.p <= kRegMaxP) {
             r.p = g.p;
             r.blocks = g.k;
@@ -686,14 +690,16 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
     }
     for (int dtype = 0; dtype < 2; ++dtype) {
         for (int p = 0; p <= kRegMaxP; ++p) {
+            for (int gm = 0; gm < 2; ++gm) {
             std::vector<RegRun> group;
             for (const RegRun& r : runs)
-                if (r.dtype == dtype && r.p == p) group.push_back(r);
+                if (r.dtype == dtype && r.p == p && r.grid_mode == gm) group.push_back(r);
             for (size_t q0 = 0; q0 < group.size(); q0 += kPack) {
                 const int n = (int)std::min<size_t>(kPack, group.size() - q0);
                 hipError_t e = dtype == 0 ? launch_reg_any<uint8_t>(p, group.data() + q0, n, stream)
                                           : launch_reg_any<uint16_t>(p, group.data() + q0, n, stream);
                 if (e != hipSuccess) return e;
+            }
             }
         }
     }
@@ -746,8 +752,8 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
 }
 
 hipError_t launch_fht(const void* img, int dtype, const Geometry& g, const TableSet& tables,
-                      void* scratch, hipStream_t stream) {
-    FhtJobSpec j{img, dtype, g, tables, scratch};
+                      void* scratch, hipStream_t stream, int grid_mode) {
+    FhtJobSpec j{img, dtype, g, tables, scratch, grid_mode};
     return launch_fht_jobs(&j, 1, stream);
 }
 

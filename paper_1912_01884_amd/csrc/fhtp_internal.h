@@ -70,12 +70,13 @@ struct FhtJobSpec {
     Geometry g;
     TableSet tables;
     void* scratch;  // fht_scratch_bytes(g)
+    int grid_mode = 0;  // 0: resident grid looping over the items; 1: one workgroup per item
 };
 // Band tables of several images, launched in packs that share kernels.
 hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream);
 // Writes the tables of one image.  dtype 0 = uint8, 1 = uint16.
 hipError_t launch_fht(const void* img, int dtype, const Geometry& g, const TableSet& tables,
-                      void* scratch, hipStream_t stream);
+                      void* scratch, hipStream_t stream, int grid_mode = 0);
 
 // ---- DP ---------------------------------------------------------------------
 // How the DP step takes its range maximum.
@@ -87,6 +88,9 @@ struct DpPlan {
     double tan_gamma;   // mode 1
     bool a16;           // back-pointers stored as uint16 (D > 256) instead of uint8
     int dc;             // displacements per thread in the fixed-window step (8 or 16)
+    bool pairs = true;  // two steps per launch where the window allows it
+    int stripe = 16;    // column tiles per stripe of the two-step kernel's item order
+    int fht_grid = 0;   // the detection's FHT: 0 resident grid, 1 one workgroup per item
 };
 
 struct DpBuffers {

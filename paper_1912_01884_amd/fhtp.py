@@ -37,7 +37,7 @@ EXPORTED = (
     "fhtp_detect_batch", "fhtp_detect_ex_workspace_bytes", "fhtp_detect_polyline_ex",
     "fhtp_prepare_image", "fhtp_plan_create", "fhtp_plan_capture", "fhtp_plan_launch",
     "fhtp_plan_destroy", "fhtp_timing_start", "fhtp_timing_stop", "fhtp_noalloc_scratch_bytes",
-    "fhtp_detect_polyline_noalloc",
+    "fhtp_detect_polyline_noalloc", "fhtp_tune_set", "fhtp_tune_get",
 )
 
 
@@ -61,6 +61,17 @@ class Job(C.Structure):
 
     _fields_ = [("img", C.c_void_p), ("dtype", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
                 ("k", C.c_int32), ("bend", Bend), ("score", C.c_void_p), ("xs", C.c_void_p)]
+
+
+class TuneRule(C.Structure):
+    """fhtp_tune_rule: launch shapes for the requests a rule covers (see fhtp.h)."""
+
+    _fields_ = [("dtype", C.c_int32), ("log2n", C.c_int32), ("w_min", C.c_int32),
+                ("w_max", C.c_int32), ("window", C.c_int32), ("dc", C.c_int32),
+                ("pairs", C.c_int32), ("stripe", C.c_int32), ("fht_grid", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class KernelTime(C.Structure):
@@ -126,6 +137,8 @@ def lib() -> C.CDLL:
     L.fhtp_plan_launch.argtypes = [vp, vp]
     L.fhtp_plan_destroy.argtypes = [vp]
     L.fhtp_timing_start.argtypes = []
+    L.fhtp_tune_set.argtypes = [C.POINTER(TuneRule), i32]
+    L.fhtp_tune_get.argtypes = [C.POINTER(TuneRule), i32, C.POINTER(C.c_int)]
     L.fhtp_noalloc_scratch_bytes.argtypes = []
     L.fhtp_detect_polyline_noalloc.argtypes = [vp, i32, i32, i32, i32, Bend, vp, vp, vp]
     L.fhtp_timing_stop.argtypes = [C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
@@ -186,6 +199,23 @@ def detect_ex_workspace_bytes(dtype: int, h: int, w: int, k: int, bend: Bend,
                                                 C.byref(out)),
            "detect_ex_workspace_bytes")
     return out.value
+
+
+def tune_set(rules) -> None:
+    """Install tuning rules (dicts with the fhtp_tune_rule fields, or TuneRule);
+    an empty list clears them."""
+    objs = [r if isinstance(r, TuneRule) else TuneRule(**r) for r in rules]
+    arr = (TuneRule * max(1, len(objs)))(*objs)
+    _check(lib().fhtp_tune_set(arr if objs else None, len(objs)), "tune_set")
+
+
+def tune_get() -> list:
+    """The installed tuning rules as dicts, in match order."""
+    cnt = C.c_int()
+    _check(lib().fhtp_tune_get(None, 0, C.byref(cnt)), "tune_get")
+    arr = (TuneRule * max(1, cnt.value))()
+    _check(lib().fhtp_tune_get(arr, cnt.value, C.byref(cnt)), "tune_get")
+    return [arr[q].as_dict() for q in range(cnt.value)]
 
 
 def timing_start() -> None:
