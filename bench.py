@@ -31,7 +31,20 @@ HBM_PEAK_GBPS = 8000.0
 # for a copy of a known size in the same run (`bench.py --summarize-counters`).
 # Valid only for the kernel source they were taken on (sha256 of the file);
 # otherwise the traffic is unknown and reported as null.
-TRAFFIC = {}
+TRAFFIC = {
+    "fht_reg_kernel": {"source": "paper_1912_01884_amd/csrc/fhtp_fht.hip",
+                      "source_sha256": "c4cdfdee5752d61ee931c9c875ecba528db41ba909d19c93e1e41e3b921ca8aa",
+                      "fetch_bytes": 41707950, "write_bytes": 151386560},
+    "dp_pair_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
+                     "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
+                     "fetch_bytes": 13989841, "write_bytes": 6653440},
+    "dp_step_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
+                     "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
+                     "fetch_bytes": 8698280, "write_bytes": 6144},
+    "walk": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
+            "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
+            "fetch_bytes": 135535, "write_bytes": 192},
+}
 
 
 def byte_model(h, w, k, bpp):
@@ -336,7 +349,9 @@ def kernel_breakdown(step, reps):
             for name, (n, ms) in fam.items()}
 
 
-def roofline_of(family, info, model):
+def roofline_of(family, info, model, headline=True):
+    """Roofline entry of a kernel family; the counter traffic (taken on the
+    4096x4096 workload) only for that workload."""
     per = info["launches_per_detection"]
     alg = kernel_alg_bytes(family, model, per)
     if alg is None:
@@ -344,7 +359,8 @@ def roofline_of(family, info, model):
     t = info["avg_launch_us"] * 1e-6
     gbps = alg / t / 1e9
     out = {"bound": "hbm", "kernel": family, "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
-           "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_of(family),
+           "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+           "traffic": traffic_of(family) if headline else None,
            "algorithmic_bytes": alg, "avg_launch_us": info["avg_launch_us"],
            "launches_per_detection": per}
     if out["traffic"] is not None:
@@ -353,6 +369,65 @@ def roofline_of(family, info, model):
         out["traffic_frac"] = round(tg / HBM_PEAK_GBPS, 4)
         out["traffic_over_algorithmic"] = round(out["traffic"] / alg, 3)
     return out
+
+
+def other_config(name, steps, warmup, dev, stream, tune=True):
+    """A smaller workload (the 64x64 or 1024x1024 image) timed like the
+    headline step, with its kernel breakdown and the answer checked against
+    the oracle."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_1912_01884_amd import autotune, fhtp
+
+    s = synth.make_config(name)
+    h, w, k, B = s.h, s.w, s.k, s.bend
+    img = torch.from_numpy(s.image).to(dev)
+    dt = fhtp.FHTP_U8 if s.image.dtype.itemsize == 1 else fhtp.FHTP_U16
+    ws = torch.empty(fhtp.detect_workspace_bytes(dt, h, w, k, fhtp.make_bend(B)), dtype=torch.uint8,
+                     device=dev)
+    score = torch.empty(1, dtype=torch.int32, device=dev)
+    xs = torch.empty(k + 1, dtype=torch.int32, device=dev)
+
+    def step():
+        fhtp.detect_polyline(img, k, bend=B, ws=ws, score=score, xs=xs, stream=stream)
+
+    previous = fhtp.tune_get()
+    tuning = None
+    if tune:
+        tuning = autotune.tune([img], [k], bends=[B], reps=max(5, steps // 2), stream=stream)
+    try:
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ms_eager = time_events(step, steps, stream)
+        got = (int(score.cpu()[0]), xs.cpu().numpy().tolist())
+        kernels = kernel_breakdown(step, max(5, steps // 2))
+        # the same detection replayed as a recorded graph (one launch per step)
+        plan = fhtp.Plan([img], [k], bends=[B], scores=[score], xss=[xs])
+        for _ in range(warmup):
+            plan.launch(stream)
+        torch.cuda.synchronize()
+        ms_graph = time_events(lambda: plan.launch(stream), steps, stream)
+        got_graph = (int(score.cpu()[0]), xs.cpu().numpy().tolist())
+        plan.destroy()
+    finally:
+        fhtp.tune_set(previous)
+    ms = min(ms_eager, ms_graph)
+    want = oracle.detect_polyline(s.image, k, bend=B)
+    model = byte_model(h, w, k, s.image.dtype.itemsize)
+    g = model["total"] / (ms * 1e-3) / 1e9
+    return {"workload": f"{h}x{w} {s.image.dtype.name} image, k={k} bands of {h // k} rows, "
+                        f"bend bound {B} shifts",
+            "ms_per_detection": round(ms, 4), "eager_ms": round(ms_eager, 4),
+            "graph_ms": round(ms_graph, 4), "mpix_per_s": round(h * w / (ms * 1e-3) / 1e6, 2),
+            "images_per_s": round(1e3 / ms, 1), "kernels": kernels,
+            "roofline_detection": {"achieved": round(g, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                   "frac": round(g / HBM_PEAK_GBPS, 4),
+                                   "algorithmic_bytes": model["total"]},
+            "tuned_rules": None if tuning is None else tuning.rules,
+            "parity": got == got_graph == (int(want[0]), [int(v) for v in want[1]])}
 
 
 def copy_bandwidth(dev, stream, reps=10):
@@ -503,6 +578,8 @@ def main():
                     help="requests per arrival rate in the serving run (0 skips it)")
     ap.add_argument("--serve-rates", default="200,1000,5000,inf",
                     help="Poisson arrival rates (requests/s) of the serving run; inf = all at once")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the 64x64 and 1024x1024 workloads")
     ap.add_argument("--no-tune", action="store_true",
                     help="run with the library's default launch shapes (no autotuning)")
     ap.add_argument("--plan-out", default=None,
@@ -616,7 +693,8 @@ def main():
 
     model = byte_model(h, w, k, bpp)
     # The kernel with the most time per detection carries the roofline object.
-    roofs = {f: roofline_of(f, info, model) for f, info in kernels.items()}
+    headline = (h, w, k, bpp) == (4096, 4096, 32, 2)
+    roofs = {f: roofline_of(f, info, model, headline) for f, info in kernels.items()}
     ranked = sorted((f for f in roofs if roofs[f] is not None),
                     key=lambda f: -kernels[f]["us_per_detection"])
     dominant = ranked[0] if ranked else None
@@ -707,6 +785,10 @@ def main():
                                                 stream=stream), max(3, args.steps // 5), stream), 4),
         }
         del wsp
+    if args.config == "4096x4096" and not args.no_other_configs:
+        line["other_configs"] = {c: other_config(c, max(20, args.steps), args.warmup, dev, stream,
+                                                 tune=not args.no_tune)
+                                 for c in ("64x64", "1024x1024")}
     if args.batch_images > 0:
         line["mixed_batch"] = mixed_batch(args.batch_images, max(3, args.steps // 10), dev, stream,
                                           tune=not args.no_tune, plan_out=args.plan_out)
@@ -725,7 +807,8 @@ def main():
         want = oracle.detect_polyline(s.image, k, bend=B)
         want = (int(want[0]), [int(v) for v in want[1]])
     # The timed detection's answer (eager calls and graph replays) against the oracle.
-    line["parity"] = bool(result == want and graph_result == want)
+    line["parity"] = bool(result == want and graph_result == want and
+                          all(o["parity"] for o in line.get("other_configs", {}).values()))
     line["result"] = {"score": result[0], "x0": result[1][0], "xk": result[1][-1]}
     print(json.dumps(line), flush=True)
     if not line["parity"]:
