@@ -170,7 +170,7 @@ DetectLayout detect_layout(const fhtp::Geometry& g, const fhtp::DpPlan& pl, fhtp
     L.narrow = fhtp::narrow_tables_apply(g, (int)dtype) ? g.k - 1 : 0;
     L.wide = align_up(L.tables + (size_t)L.narrow * band * sizeof(uint16_t));
     L.scratch = align_up(L.wide + (size_t)(g.k - L.narrow) * band * sizeof(int32_t));
-    L.dp = dp_layout(g, pl, align_up(L.scratch + fhtp::fht_scratch_bytes(g)));
+    L.dp = dp_layout(g, pl, align_up(L.scratch + fhtp::fht_scratch_bytes(g, (int)dtype)));
     return L;
 }
 
@@ -256,7 +256,7 @@ int fhtp_fht_workspace_bytes(fhtp_dtype dtype, int h, int w, int k, size_t* byte
     int rc = shape(h, w, k, &g);
     if (rc == FHTP_OK) rc = pixels(dtype, h);
     if (rc != FHTP_OK) return rc;
-    *bytes = fhtp::fht_scratch_bytes(g);
+    *bytes = fhtp::fht_scratch_bytes(g, (int)dtype);
     return FHTP_OK;
 }
 
@@ -266,7 +266,7 @@ int fhtp_fht_bands(const void* img, fhtp_dtype dtype, int h, int w, int k, int32
     fhtp::Geometry g;
     int rc = shape(h, w, k, &g);
     if (rc == FHTP_OK) rc = pixels(dtype, h);
-    if (rc == FHTP_OK) rc = check_ws(ws, ws_bytes, fhtp::fht_scratch_bytes(g));
+    if (rc == FHTP_OK) rc = check_ws(ws, ws_bytes, fhtp::fht_scratch_bytes(g, (int)dtype));
     if (rc != FHTP_OK) return rc;
     (void)hipGetLastError();
     return hip_status(fhtp::launch_fht(img, (int)dtype, g, wide_tables(tables), ws,

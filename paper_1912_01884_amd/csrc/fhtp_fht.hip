@@ -211,6 +211,7 @@ struct FhtJob {
     int item0;        // first work item of this run in the launch
     int to_table;     // 1: band tables; 0: c-space sub-block scratch
     int narrow;       // bands stored as uint16 (the rest, from band `narrow` on, go to out)
+    int sub16;        // scratch as uint16 (8-bit pixels: a 128-row sum is at most 32640)
 };
 
 constexpr int kPack = 256;  // runs per launch (kernel arguments of up to 32 KB)
@@ -349,6 +350,16 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
                 __builtin_amdgcn_raw_buffer_store_b32(
                     v[s], r, (int)voff, (int)((unsigned int)(N - 1 - s) * row_bytes), 0);
         }
+    } else if (J.sub16) {
+        const unsigned int row16 = (unsigned int)W * 2u;
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(
+            reinterpret_cast<uint16_t*>(J.out) + (size_t)(it.blk * C::NDIR + it.dir) * N * (size_t)W,
+            (unsigned int)N * row16);
+        const unsigned int voff = (unsigned int)it.c * 2u;
+#pragma unroll
+        for (int s = 0; s < N; ++s)
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v[s], r, (int)voff,
+                                                  (int)((unsigned int)s * row16), 0);
     } else {
         const __amdgpu_buffer_rsrc_t r =
             make_rsrc(J.out + (size_t)(it.blk * C::NDIR + it.dir) * N * (size_t)W,
@@ -451,12 +462,13 @@ __global__ __launch_bounds__(RegCfg<P>::NT) void fht_reg_kernel(FhtPack<CAP> pk)
 // A workgroup covers 256 columns of one (band, direction) for kShiftGroup
 // consecutive shifts; the offsets D_s(128 m) are uniform (scalar) per shift.
 struct CombineJob {
-    const int32_t* sub;
+    const void* sub;   // [sub-blocks][2][128][W] int32, or uint16 for 8-bit pixels (sub16)
     int32_t* tables;   // wide bands (from band `narrow` on), [.][2n-1][W] int32
     uint16_t* tab16;   // narrow bands 0 .. narrow-1, [.][2n-1][W] uint16
     int p, W, k, tiles_x;
     int item0;
     int narrow;
+    int sub16;
 };
 
 struct CombinePack {
@@ -479,7 +491,8 @@ __device__ __forceinline__ int sub_block_offset(int s, int m) {
     return off;
 }
 
-template <int SH>  // SH = p - 7, M = 2^SH sub-blocks per band
+// SH = p - 7, M = 2^SH sub-blocks per band; SubT: the scratch's cell type.
+template <int SH, typename SubT>
 __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
     constexpr int M = 1 << SH;
     const int item = blockIdx.x;
@@ -507,7 +520,7 @@ __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
     const int c = tile * 256 + threadIdx.x;
     if (c >= W) return;
     const size_t row = (size_t)W;
-    const int32_t* base = J.sub + (size_t)band * M * 2 * (1 << kRegMaxP) * row;
+    const SubT* base = static_cast<const SubT*>(J.sub) + (size_t)band * M * 2 * (1 << kRegMaxP) * row;
     const bool n16 = band < J.narrow;
     int32_t* out = J.tables + (size_t)(band - J.narrow) * D * row;
     uint16_t* out16 = J.tab16 + (size_t)band * D * row;
@@ -524,7 +537,7 @@ __global__ __launch_bounds__(256) void fht_combine_kernel(CombinePack pk) {
         for (int m = 0; m < M; ++m) {
             int cc = c + sub_block_offset<SH>(s, m);
             cc -= cc >= W ? W : 0;  // offsets are below n < W, so one wrap at most
-            a += base[((size_t)(m * 2 + dir) * (1 << kRegMaxP) + sf) * row + cc];
+            a += (int32_t)base[((size_t)(m * 2 + dir) * (1 << kRegMaxP) + sf) * row + cc];
         }
         acc[t] = a;
     }
@@ -576,6 +589,7 @@ struct RegRun {
     uint16_t* out16;
     int narrow;
     int grid_mode;  // 0: resident grid; 1: one workgroup per item
+    int sub16;
 };
 
 template <int P, typename PixT, int CAP>
@@ -613,6 +627,7 @@ hipError_t launch_reg_pack(const RegRun* runs, int count, hipStream_t stream) {
         J.to_table = r.to_table;
         J.out16 = r.out16;
         J.narrow = r.narrow;
+        J.sub16 = r.sub16;
         total += (long long)tiles * r.blocks * C::NDIR;
         if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     }
@@ -653,10 +668,12 @@ hipError_t launch_reg_any(int p, const RegRun* runs, int count, hipStream_t stre
 
 }  // namespace
 
-size_t fht_scratch_bytes(const Geometry& g) {
+size_t fht_scratch_bytes(const Geometry& g, int dtype) {
     if (g.p <= kRegMaxP) return 0;
-    // [h/128 sub-blocks][2 directions][128 shifts][W] int32
-    return (size_t)(g.h >> kRegMaxP) * 2 * (1u << kRegMaxP) * (size_t)g.W * sizeof(int32_t);
+    // [h/128 sub-blocks][2 directions][128 shifts][W]: uint16 for 8-bit pixels
+    // (a 128-row line sum is at most 128 * 255), int32 for 16-bit ones
+    const size_t cell = dtype == 0 ? sizeof(uint16_t) : sizeof(int32_t);
+    return (size_t)(g.h >> kRegMaxP) * 2 * (1u << kRegMaxP) * (size_t)g.W * cell;
 }
 
 hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream) {
@@ -674,6 +691,7 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
         r.out16 = J.tables.narrow ? J.tables.tab16 : nullptr;
         r.narrow = 0;
         r.grid_mode = J.grid_mode;
+        r.sub16 = 0;
         if (g.p <= kRegMaxP) {
             r.p = g.p;
             r.blocks = g.k;
@@ -685,6 +703,7 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
             r.blocks = g.h >> kRegMaxP;
             r.to_table = 0;
             r.out = static_cast<int32_t*>(J.scratch);
+            r.sub16 = J.dtype == 0;
         }
         runs.push_back(r);
     }
@@ -709,7 +728,8 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
         const Geometry& g = jobs[q].g;
         if (g.p <= kRegMaxP) continue;
         CombineJob c;
-        c.sub = static_cast<const int32_t*>(jobs[q].scratch);
+        c.sub = jobs[q].scratch;
+        c.sub16 = jobs[q].dtype == 0;
         c.tables = jobs[q].tables.wide;
         c.tab16 = jobs[q].tables.tab16;
         c.narrow = jobs[q].tables.narrow;
@@ -721,9 +741,10 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
         comb.push_back(c);
     }
     for (int sh = 1; sh <= 3; ++sh) {
+      for (int s16 = 0; s16 < 2; ++s16) {
         std::vector<CombineJob> group;
         for (const CombineJob& c : comb)
-            if (c.p - kRegMaxP == sh) group.push_back(c);
+            if (c.p - kRegMaxP == sh && c.sub16 == s16) group.push_back(c);
         for (size_t q0 = 0; q0 < group.size(); q0 += kPack) {
             CombinePack pk{};
             const int n = (int)std::min<size_t>(kPack, group.size() - q0);
@@ -738,15 +759,26 @@ hipError_t launch_fht_jobs(const FhtJobSpec* jobs, int count, hipStream_t stream
             pk.count = n;
             pk.total = (int)total;
             TimedLaunch tl("fht_combine_kernel", stream);
-            if (sh == 1)
-                hipLaunchKernelGGL(fht_combine_kernel<1>, dim3((unsigned)total), dim3(256), 0, stream, pk);
-            else if (sh == 2)
-                hipLaunchKernelGGL(fht_combine_kernel<2>, dim3((unsigned)total), dim3(256), 0, stream, pk);
-            else
-                hipLaunchKernelGGL(fht_combine_kernel<3>, dim3((unsigned)total), dim3(256), 0, stream, pk);
+            const dim3 grid((unsigned)total), block(256);
+            if (s16) {
+                if (sh == 1)
+                    hipLaunchKernelGGL((fht_combine_kernel<1, uint16_t>), grid, block, 0, stream, pk);
+                else if (sh == 2)
+                    hipLaunchKernelGGL((fht_combine_kernel<2, uint16_t>), grid, block, 0, stream, pk);
+                else
+                    hipLaunchKernelGGL((fht_combine_kernel<3, uint16_t>), grid, block, 0, stream, pk);
+            } else {
+                if (sh == 1)
+                    hipLaunchKernelGGL((fht_combine_kernel<1, int32_t>), grid, block, 0, stream, pk);
+                else if (sh == 2)
+                    hipLaunchKernelGGL((fht_combine_kernel<2, int32_t>), grid, block, 0, stream, pk);
+                else
+                    hipLaunchKernelGGL((fht_combine_kernel<3, int32_t>), grid, block, 0, stream, pk);
+            }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
+      }
     }
     return hipSuccess;
 }

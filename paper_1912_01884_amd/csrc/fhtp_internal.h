@@ -60,8 +60,9 @@ inline bool narrow_tables_apply(const Geometry& g, int dtype) {
 }
 
 // ---- band FHT -------------------------------------------------------------
-// Scratch needed by launch_fht (bytes, 0 when n <= 2^kRegMaxP).
-size_t fht_scratch_bytes(const Geometry& g);
+// Scratch needed by launch_fht (bytes, 0 when n <= 2^kRegMaxP); dtype 0 =
+// uint8 pixels (16-bit scratch cells), 1 = uint16 pixels (32-bit cells).
+size_t fht_scratch_bytes(const Geometry& g, int dtype);
 
 // One image's band FHT.
 struct FhtJobSpec {
@@ -69,7 +70,7 @@ struct FhtJobSpec {
     int dtype;  // 0 = uint8, 1 = uint16
     Geometry g;
     TableSet tables;
-    void* scratch;  // fht_scratch_bytes(g)
+    void* scratch;  // fht_scratch_bytes(g, dtype)
     int grid_mode = 0;  // 0: resident grid looping over the items; 1: one workgroup per item
 };
 // Band tables of several images, launched in packs that share kernels.
