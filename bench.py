@@ -33,14 +33,14 @@ HBM_PEAK_GBPS = 8000.0
 # otherwise the traffic is unknown and reported as null.
 TRAFFIC = {
     "fht_reg_kernel": {"source": "paper_1912_01884_amd/csrc/fhtp_fht.hip",
-                      "source_sha256": "c4cdfdee5752d61ee931c9c875ecba528db41ba909d19c93e1e41e3b921ca8aa",
-                      "fetch_bytes": 41707950, "write_bytes": 151386560},
+                      "source_sha256": "e3cdf11d01e858cd2cdd5454bc92dd819b4aeca9c3ccca1ab77b38906fe3cc4b",
+                      "fetch_bytes": 41997953, "write_bytes": 151428160},
     "dp_pair_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
                      "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
-                     "fetch_bytes": 13989841, "write_bytes": 6653440},
+                     "fetch_bytes": 13989872, "write_bytes": 6653440},
     "dp_step_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
                      "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
-                     "fetch_bytes": 8698280, "write_bytes": 6144},
+                     "fetch_bytes": 8698177, "write_bytes": 6144},
     "walk": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
             "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
             "fetch_bytes": 135535, "write_bytes": 192},
@@ -507,7 +507,7 @@ def summarize_trace(folder):
     starts = [q for q, e in enumerate(seq) if e[2].startswith("fht_reg_kernel")]
     for q0 in reversed(starts):
         q1 = next((q for q in range(q0, len(seq)) if seq[q][2].startswith("walk")), None)
-        if q1 is None or any("true>" in e[2] for e in seq[q0:q1 + 1]):
+        if q1 is None or any(", true" in e[2] for e in seq[q0:q1 + 1]):
             continue  # incomplete, or a through-point query (pinned kernels)
         print("\nOne detection (the last unpinned one traced; kernels in launch order):\n")
         run = {}

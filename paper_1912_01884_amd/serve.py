@@ -226,13 +226,26 @@ class Server:
 
 # ---- the GPU backend ---------------------------------------------------------
 
+def request_bytes_cached(F, cache: dict, r: Request) -> int:
+    """fhtp_detect_workspace_bytes of a request, looked up once per shape
+    (pixel type, h, w, k, bend restriction)."""
+    h, w = r.img.shape
+    key = (r.img.dtype, h, w, r.k, r.bend, r.gamma)
+    n = cache.get(key)
+    if n is None:
+        n = F.detect_workspace_bytes(F._dtype_code(r.img), h, w, r.k, F.make_bend(r.bend, r.gamma))
+        cache[key] = n
+    return n
+
+
 def order_after_submitter(torch, s, reqs: List[Request], device) -> None:
     """Order the detections on stream `s` after the request tensors' producers.
 
     The images, scores and vertex buffers may have been filled or allocated
     asynchronously on the stream that was current when the request was
-    submitted (`Request.producer`): `s` waits for each such stream, once per
-    distinct stream (without a recorded producer, for the stream current now).
+    submitted (`Request.producer`): `s` waits for each such stream that still
+    has work queued, once per distinct stream (without a recorded producer,
+    for the stream current now).
     The tensors themselves cannot be freed while the detection runs: the
     server holds its requests until their completion event has fired.
     """
@@ -241,7 +254,10 @@ def order_after_submitter(torch, s, reqs: List[Request], device) -> None:
         p = r.producer if r.producer is not None else torch.cuda.current_stream(device)
         if p.cuda_stream not in seen:
             seen.add(p.cuda_stream)
-            s.wait_stream(p)
+            # a producer with nothing left to run has finished every tensor
+            # submitted before now: no event needed
+            if not p.query():
+                s.wait_stream(p)
 
 
 class FhtpBackend:
@@ -264,6 +280,7 @@ class FhtpBackend:
             raise RuntimeError("no device memory available for the arena")
         self.arena = torch.empty(size, dtype=torch.uint8, device=self.device)
         self.base = self.arena.data_ptr()
+        self._bytes: dict = {}  # workspace bytes per request shape
         self.streams = [torch.cuda.Stream(self.device) for _ in range(streams)]
         # the arena's allocation is ordered before any group on any stream
         torch.cuda.synchronize(self.device)
@@ -282,9 +299,7 @@ class FhtpBackend:
                      r.xs.data_ptr())
 
     def request_bytes(self, r: Request) -> int:
-        F = self.fhtp
-        h, w = r.img.shape
-        return F.detect_workspace_bytes(F._dtype_code(r.img), h, w, r.k, F.make_bend(r.bend, r.gamma))
+        return request_bytes_cached(self.fhtp, self._bytes, r)
 
     def launch(self, reqs: List[Request], offset: int, nbytes: int, stream: int):
         jobs = [self._job(r) for r in reqs]
@@ -317,16 +332,14 @@ class PlainServer:
         self.ws = torch.empty(max(align_up(max_request_bytes), ALIGN), dtype=torch.uint8,
                               device=self.device)
         self.stream = torch.cuda.Stream(self.device)
+        self._bytes: dict = {}  # workspace bytes per request shape
         self.clock = clock
         self.waiting: Deque[Request] = collections.deque()
         self.current: Optional[Tuple[Request, Any]] = None
         torch.cuda.synchronize(self.device)
 
     def submit(self, req: Request) -> bool:
-        F = self.fhtp
-        h, w = req.img.shape
-        req.nbytes = F.detect_workspace_bytes(F._dtype_code(req.img), h, w, req.k,
-                                              F.make_bend(req.bend, req.gamma))
+        req.nbytes = request_bytes_cached(self.fhtp, self._bytes, req)
         if req.nbytes > self.ws.numel():
             req.error = "request larger than the workspace"
             return False
