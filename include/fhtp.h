@@ -298,9 +298,10 @@ int fhtp_plan_destroy(fhtp_plan plan);
  * it covers it sets:
  *   dc:       displacements per thread of one-step fixed-window launches, 8 or
  *             16 (0: the library's choice by grid size);
- *   pairs:    1: two DP steps per launch where the window allows it (needs
- *             dc 8), 0: one step per launch;
- *   stripe:   column tiles per stripe of the two-step kernel's workgroup
+ *   steps:    the most DP steps one launch takes, 1, 2 or 3 (0: the
+ *             library's choice, 2); two and three need dc 8 (or 0), three a
+ *             bound of at most 8 shifts and no through-point pin (else two);
+ *   stripe:   column tiles per stripe of the multi-step kernels' workgroup
  *             order, 1..64 (0: 16);
  *   fht_grid: 0: the FHT's resident grid loops over the work items; 1: one
  *             workgroup per work item.
@@ -320,7 +321,7 @@ typedef struct {
     int32_t w_min, w_max;
     int32_t window;
     int32_t dc;
-    int32_t pairs;
+    int32_t steps;
     int32_t stripe;
     int32_t fht_grid;
 } fhtp_tune_rule;

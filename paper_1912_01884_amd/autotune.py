@@ -2,8 +2,8 @@
 
 The library cuts its work into launches and workgroups by rules that never
 change a result (fhtp_tune_set, include/fhtp.h): the displacements per thread
-of one-step DP launches, whether two DP steps share a launch, the stripe
-width of the two-step kernel's workgroup order, and whether the FHT runs a
+of one-step DP launches, how many DP steps (one, two or three) share a
+launch, the stripe width of the multi-step kernels' workgroup order, and whether the FHT runs a
 resident grid or one workgroup per work item.  ``tune`` times the candidates
 on the caller's own images through the batched entry point (the shapes a
 workload really launches, packed as they really are), checks that every
@@ -35,17 +35,17 @@ from . import fhtp
 
 W_ANY = (0, 1 << 20)
 
-# Two steps per launch at four stripe widths, one step per launch at 8 and 16
-# displacements per thread.
-DP_CANDIDATES = ([dict(dc=8, pairs=1, stripe=s) for s in (4, 8, 16, 32)] +
-                 [dict(dc=8, pairs=0, stripe=0), dict(dc=16, pairs=0, stripe=0)])
+# Three and two steps per launch at four stripe widths each, one step per
+# launch at 8 and 16 displacements per thread.
+DP_CANDIDATES = ([dict(dc=8, steps=g, stripe=s) for g in (3, 2) for s in (4, 8, 16, 32)] +
+                 [dict(dc=8, steps=1, stripe=0), dict(dc=16, steps=1, stripe=0)])
 FHT_CANDIDATES = (0, 1)
 
 
-def rule(dtype=-1, log2n=-1, window=-1, dc=0, pairs=1, stripe=0, fht_grid=0,
+def rule(dtype=-1, log2n=-1, window=-1, dc=0, steps=0, stripe=0, fht_grid=0,
          w_min=W_ANY[0], w_max=W_ANY[1]) -> dict:
     return dict(dtype=int(dtype), log2n=int(log2n), w_min=int(w_min), w_max=int(w_max),
-                window=int(window), dc=int(dc), pairs=int(pairs), stripe=int(stripe),
+                window=int(window), dc=int(dc), steps=int(steps), stripe=int(stripe),
                 fht_grid=int(fht_grid))
 
 
@@ -154,7 +154,7 @@ def tune(images: Sequence, ks: Sequence[int], bends=None, gammas=None, reps: int
 
         best_dp, best_ms = None, float("inf")
         for cand in DP_CANDIDATES:
-            name = "dp dc{dc} pairs{pairs} stripe{stripe}".format(**cand)
+            name = "dp dc{dc} steps{steps} stripe{stripe}".format(**cand)
             ms = trial(name, _rules_for(wl.groups, cand, {}))
             if ms < best_ms:
                 best_dp, best_ms = cand, ms
@@ -203,7 +203,7 @@ def load(path: str, install_rules: bool = True) -> Optional[List[dict]]:
         doc = json.load(f)
     if doc.get("key") != device_key():
         return None
-    rules = [rule(**{k: r[k] for k in ("dtype", "log2n", "window", "dc", "pairs", "stripe",
+    rules = [rule(**{k: r[k] for k in ("dtype", "log2n", "window", "dc", "steps", "stripe",
                                        "fht_grid", "w_min", "w_max")})
              for r in doc["rules"]]
     if install_rules:

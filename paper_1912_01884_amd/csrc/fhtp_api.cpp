@@ -78,7 +78,7 @@ std::vector<fhtp_tune_rule> g_tune;
 bool rule_valid(const fhtp_tune_rule& r) {
     return r.dtype >= -1 && r.dtype <= 1 && r.log2n >= -1 && r.log2n <= 10 && r.w_min >= 0 &&
            r.w_min <= r.w_max && r.window >= -1 && r.window <= 1 &&
-           (r.dc == 0 || r.dc == 8 || r.dc == 16) && (r.pairs == 0 || r.pairs == 1) &&
+           (r.dc == 0 || r.dc == 8 || r.dc == 16) && (r.steps >= 0 && r.steps <= 3) &&
            r.stripe >= 0 && r.stripe <= 64 && (r.fht_grid == 0 || r.fht_grid == 1);
 }
 
@@ -93,7 +93,7 @@ void apply_tuning(const fhtp::Geometry& g, int dtype, fhtp::DpPlan* pl) {
         if (g.w < r.w_min || g.w > r.w_max) continue;
         if (r.window != -1 && r.window != window) continue;
         if (r.dc) pl->dc = r.dc;
-        pl->pairs = r.pairs != 0;
+        if (r.steps) pl->steps = r.steps;
         pl->stripe = r.stripe ? r.stripe : 16;
         pl->fht_grid = r.fht_grid;
         return;
@@ -104,7 +104,7 @@ void apply_tuning(const fhtp::Geometry& g, int dtype, fhtp::DpPlan* pl) {
 int plan_window(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
     pl->a16 = g.D > 256;
     pl->dc = dp_chunk(g);
-    pl->pairs = true;
+    pl->steps = 2;
     pl->stripe = 16;
     pl->fht_grid = 0;
     pl->bound = 0;

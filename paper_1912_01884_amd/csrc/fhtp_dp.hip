@@ -35,7 +35,8 @@
 // applied where the table H_{k-1} is read as V_{k-1}.  Every other bend stays
 // bounded as usual, so the result is the best polyline through the point.
 //
-// With the fixed window, two steps share a launch (dp_pair_fixed): a step
+// With the fixed window, two steps share a launch (dp_pair_fixed; three with
+// dp_triple_fixed where a tuning rule asks for it): a step
 // reads V_{i+1} only in its own successor columns and in its displacement rows
 // widened by the bound, so a workgroup computes exactly those cells of V_{i+1}
 // from V_{i+2} in LDS and goes on to step i, and V_{i+1} never goes through
@@ -110,10 +111,15 @@ struct WalkJob {
     int n_keys, a_pitch;
     int n, w, k;
     int bound, full;
-    // Bands 1 .. pair_top were made two per launch (0: none).  For odd i <
-    // pair_top, plane i holds, at the cell (d_i, x_{i+1}) of plane i-1, the link
-    // d_{i+2} that follows d_{i+1}: both links of a pair are read at one index.
-    int pair_top;
+    // Bands pair_lo .. pair_top were made two per launch (pair_top 0: none).
+    // For i = pair_lo, pair_lo + 2, ... < pair_top, plane i holds, at the cell
+    // (d_i, x_{i+1}) of plane i-1, the link d_{i+2} that follows d_{i+1}: both
+    // links of a pair are read at one index.
+    int pair_lo, pair_top;
+    // Bands 1 .. tri_top were made three per launch (0: none): for i = 1, 4,
+    // 7, ..., planes i-1, i and i+1 hold d_{i+1}, d_{i+2} and d_{i+3} at the
+    // one index (d_i, x_{i+1}).
+    int tri_top;
 };
 
 template <int CAP>
@@ -814,6 +820,273 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     }
 }
 
+// Three steps per launch (fixed windows of at most kTriMaxB shifts): the
+// two-step scheme one level deeper.  A workgroup owns the cells of step i in
+// 64 successor columns x' and 32 displacements, as in dp_pair_fixed.  Those
+// read V_{i+1} in the same columns and the displacement rows widened by B;
+// these read V_{i+2} at columns x'' = x' + d' and rows widened by 2B, which
+// for a displacement row d'' are the 64 + 2B columns x'' - d'' in
+// [X0 - B, X0 + 63 + B].  So
+//   level 2: V_{i+2} over those cells from V_{i+3} in memory, into LDS stored
+//            skewed (column x'' - d'' - X0 + B of row d''), each cell with the
+//            row of its window maximum (its choice);
+//   level 1: V_{i+1} over the widened rows of the tile from level 2, each cell
+//            with its choice and its choice's choice;
+//   level 0: step i, writing V_i and at each of its cells the three links of
+//            its chain: A_{i+1}, A_{i+2} and A_{i+3} at the same index.
+// Level 2 runs in strips of kStrip rows as the pair's phase 1 does: a thread
+// owns a column x''' of V_{i+3}, and its cells (x''' - d'', d'') of a strip lie
+// on a diagonal; the strip's cells lie in 64 + 2B + 2(kStrip - 1) columns
+// x'''.  Level 1 is the pair's phase 1 with the loads of V_{i+2} taken from
+// LDS.  About twice the cells of a pair launch for one and a half times its
+// steps, and a third of the launches of one step each.  Measured on the
+// 4096 x 4096 image (k = 32, bound 8): a wave issues 1465 VALU instructions
+// against the pair kernel's 646, and a launch takes 12.3 us against 6.4, so
+// ten launches of three steps cost more than fifteen of two; the library
+// takes three steps per launch only where a tuning rule asks for them.
+constexpr int kTriMaxB = 8;
+
+struct DpTripleJob {
+    const int32_t* vin;  // V_{i+3} (or the table H_{k-1}), rows d'''+n-1
+    const void* h2;      // H_{i+2} (int32, or uint16 for narrow tables: the kernel's TT)
+    const void* h1;      // H_{i+1}
+    const void* h0;      // H_i
+    int32_t* vout;       // V_i
+    void* a2;            // A_{i+3} plane: at each cell of step i, the third link
+    void* a1;            // A_{i+2} plane: the second link
+    void* a0;            // A_{i+1} plane: the cell's own choice
+    int vin_pitch, h_pitch, v_pitch, a_pitch;
+    int n, w, items_x, items_y;
+    int item0;  // first workgroup of this image in the launch
+};
+
+template <int CAP>
+struct DpTriplePack {
+    DpTripleJob job[CAP];
+    int count;
+    int stripe;  // column tiles per stripe of the item order
+};
+
+template <int B, typename AT, int CAP, typename TT>
+__global__ __launch_bounds__(64 * kPairWaves) void dp_triple_fixed(DpTriplePack<CAP> pk) {
+    static_assert(B <= kTriMaxB, "three steps per launch take bounds of at most kTriMaxB");
+    constexpr int R1 = kPairRows + 2 * B;  // rows of V_{i+1} the workgroup needs
+    constexpr int NS1 = (R1 + kStrip - 1) / kStrip;
+    constexpr int R2 = kPairRows + 4 * B;  // rows of V_{i+2}
+    constexpr int NS2 = (R2 + kStrip - 1) / kStrip;
+    constexpr int SC1 = 64 + kStrip - 1;                 // columns x'' of a level-1 strip
+    constexpr int SC2 = 64 + 2 * B + 2 * (kStrip - 1);  // columns x''' of a level-2 strip
+    constexpr int NV = kStrip + 2 * B;                   // window rows of a strip's cells
+    constexpr int NV0 = kPairDC + 2 * B;
+    constexpr int esz = (int)sizeof(AT);
+    constexpr int LP = kStrip - 1;
+    constexpr int LWP = 64 + 2 * LP;  // level-1 row: the tile's columns and padding
+    constexpr int P2 = kStrip - 1;
+    constexpr int LW2 = 64 + 2 * B + 2 * P2;  // level-2 row (skewed) and padding
+    constexpr int ROWS2 = NS1 * kStrip + 2 * B > NS2 * kStrip ? NS1 * kStrip + 2 * B : NS2 * kStrip;
+    static_assert(NS1 * SC1 <= 64 * kPairWaves, "level 1 takes one round of the workgroup");
+    __shared__ int lv2[ROWS2][LW2];  // V_{i+2}(x'', row g0 + q) at [q][x'' - d'' - X0 + B + P2]
+    __shared__ AT ch2[ROWS2][LW2];   // row of that cell's window maximum
+    __shared__ int mid[NS1 * kStrip][LWP];  // V_{i+1}(X0 + c, row m0 + q) at [q][LP + c]
+    __shared__ AT nx1[NS1 * kStrip][LWP];   // its choice (a row of V_{i+2})
+    __shared__ AT nx2[NS1 * kStrip][LWP];   // its choice's choice (a row of V_{i+3})
+
+    // Item order as in dp_pair_fixed: contiguous runs per XCD, walked in
+    // stripes of pk.stripe column tiles.
+    const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);
+    int jj = 0;
+    if constexpr (CAP > 1) {
+        int hi = pk.count - 1;
+        while (jj < hi) {
+            const int md = (jj + hi + 1) >> 1;
+            if (pk.job[md].item0 <= it)
+                jj = md;
+            else
+                hi = md - 1;
+        }
+    }
+    const DpTripleJob& a = pk.job[jj];
+    const int n = a.n, w = a.w;
+    const int D = 2 * n - 1;
+    int bx, by;
+    {
+        const int local = CAP > 1 ? it - a.item0 : it;
+        const int stripe = pk.stripe;
+        const int per_stripe = stripe * a.items_y;
+        const int st = local / per_stripe, loc = local - st * per_stripe;
+        const int sw = min(stripe, a.items_x - st * stripe);
+        by = loc / sw;
+        bx = st * stripe + (loc - by * sw);
+    }
+    const int X0 = bx * 64;
+    const int r0 = by * kPairRows;  // table row of the first displacement of step i
+    const int m0 = r0 - B;          // table row of mid[0]
+    const int g0 = r0 - 2 * B;      // table row of lv2[0]
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr unsigned int hsz = sizeof(TT);
+    const unsigned int hp = (unsigned int)a.h_pitch * hsz;
+
+    // Level 0's H_i(x' - d, d) and level 1's H_{i+1}, issued first so that
+    // the loads overlap level 2.
+    const int xp = X0 + lane;
+    const bool col_ok = xp < w;
+    const int r2 = r0 + wave * kPairDC;
+    const int d2 = r2 - (n - 1);
+    const RowView h0v = row_view(a.h0, a.h_pitch, (int)hsz, r2, kPairDC, D);
+    const unsigned int h0b = (unsigned int)(r2 - h0v.base) * hp + (unsigned int)(xp - d2) * hsz;
+    int hv0[kPairDC];
+#pragma unroll
+    for (int j = 0; j < kPairDC; ++j) hv0[j] = load_tab<TT>(h0v.rs, h0b + j * (hp - hsz), 0);
+
+    const int t1 = threadIdx.x;  // level-1 task: strip s1, column c1
+    const bool has1 = t1 < NS1 * SC1;
+    const int s1 = has1 ? t1 / SC1 : 0;
+    const int c1 = has1 ? t1 - s1 * SC1 : 0;
+    const int q1 = s1 * kStrip;   // mid row of the strip's first displacement
+    const int rs1 = m0 + q1;      // its table row
+    const int x1s = X0 + rs1 - (n - 1) + c1;  // the strip column x''
+    const RowView h1v = row_view(a.h1, a.h_pitch, (int)hsz, m0, R1, D);
+    int hv1[kStrip];
+    {
+        const unsigned int hb =
+            (unsigned int)(rs1 - h1v.base) * hp + (unsigned int)(X0 + c1) * hsz;
+#pragma unroll
+        for (int j = 0; j < kStrip; ++j) hv1[j] = load_tab<TT>(h1v.rs, hb + j * (hp - hsz), 0);
+    }
+
+    // Level 2.  Views: V_{i+3} rows [g0 - B, g0 + NS2*kStrip + B), H_{i+2}
+    // rows [g0, g0 + NS2*kStrip), each clipped to [0, D).
+    const RowView vv = row_view(a.vin, a.vin_pitch, 4, g0 - B, NS2 * kStrip + 2 * B, D);
+    const RowView h2v = row_view(a.h2, a.h_pitch, (int)hsz, g0, NS2 * kStrip, D);
+    const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
+    for (int t = threadIdx.x; t < NS2 * SC2; t += 64 * kPairWaves) {
+        const int s = t / SC2, c = t - s * SC2;
+        const int q0 = s * kStrip;
+        const int rs = g0 + q0;             // table row of the strip's first displacement
+        const int ds = rs - (n - 1);        // that displacement
+        const int xs = X0 + 2 * ds - B + c;  // the thread's column x''' of V_{i+3}
+        const bool xs_ok = (unsigned)xs < (unsigned)w;
+        // v[q] = V_{i+3}(x''', row rs - B + q): a cell when the row lies in
+        // [0, D) and x''' and x''' plus its displacement lie in [0, w)
+        const int rlo = rs - B;
+        const int qlo = max(-rlo, (n - 1) - xs - rlo);
+        const int qhi = xs_ok ? min(D - rlo, w + (n - 1) - xs - rlo) : qlo;
+        // cell j is (x'', row rs + j) with x'' = x''' - ds - j: it exists when
+        // the row lies in [0, D), x'' in [0, w) and x''' in [0, w)
+        const int jlo = max(-rs, xs - ds - w + 1);
+        const int jhi = xs_ok ? min(D - rs, xs - ds + 1) : jlo;
+        const unsigned int vb = (unsigned int)(rlo - vv.base) * vp + (unsigned int)xs * 4u;
+        const unsigned int hb =
+            (unsigned int)(rs - h2v.base) * hp + (unsigned int)(xs - ds) * hsz;
+        // cell j lands in column c + P2 - 2j of its row; columns outside the
+        // row are cells no later level reads
+        const bool inner = qlo <= 0 && qhi >= NV && jlo <= 0 && jhi >= kStrip;
+        auto strip = [&](auto inner_tag) {
+            constexpr bool INNER = decltype(inner_tag)::value;
+            int v[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                if constexpr (INNER) {
+                    v[q] = __builtin_amdgcn_raw_buffer_load_b32(vv.rs, (int)(vb + q * vp), 0, 0);
+                } else {
+                    const bool ok = q >= qlo && q < qhi;
+                    const int tv = __builtin_amdgcn_raw_buffer_load_b32(
+                        vv.rs, (int)(ok ? vb + q * vp : kOut), 0, 0);
+                    v[q] = ok ? tv : -1;
+                }
+            }
+            int hv[kStrip];
+#pragma unroll
+            for (int j = 0; j < kStrip; ++j) hv[j] = load_tab<TT>(h2v.rs, hb + j * (hp - hsz), 0);
+            __builtin_amdgcn_sched_barrier(0);
+            int m[kStrip], ia[kStrip];
+            window_max<B, kStrip>(v, m, ia);
+#pragma unroll
+            for (int j = 0; j < kStrip; ++j) {
+                const int col = c + P2 - 2 * j;
+                if ((unsigned)col < (unsigned)LW2) {
+                    const bool live = INNER || (j >= jlo && j < jhi);
+                    lv2[q0 + j][col] = live && m[j] >= 0 ? hv[j] + m[j] : -1;
+                    const int ra = rlo + ia[j];  // row of the maximum's d'''
+                    ch2[q0 + j][col] = (AT)(INNER || ra >= 0 ? ra : 0);
+                }
+            }
+        };
+        if (__builtin_amdgcn_ballot_w64(!inner) == 0)
+            strip(std::true_type{});
+        else
+            strip(std::false_type{});
+    }
+    __syncthreads();
+
+    // Level 1: the strip column x'' reads V_{i+2}(x'', row rs1 - B + t) at
+    // lv2[q1 + t][c1 + 2B - t + P2]; cells (X0 + c1 - j, row rs1 + j).
+    if (has1) {
+        const int jlo = max(-rs1, X0 + c1 - w + 1);
+        const int jhi = (unsigned)x1s < (unsigned)w ? D - rs1 : jlo;
+        int v[NV];
+        const int* src = &lv2[q1][c1 + 2 * B + P2];
+#pragma unroll
+        for (int t = 0; t < NV; ++t) v[t] = src[t * (LW2 - 1)];
+        int m[kStrip], ia[kStrip];
+        window_max<B, kStrip>(v, m, ia);
+        int* lrow = &mid[q1][LP + c1];
+        AT* nrow1 = &nx1[q1][LP + c1];
+        AT* nrow2 = &nx2[q1][LP + c1];
+        const AT* csrc = &ch2[q1][c1 + 2 * B + P2];
+#pragma unroll
+        for (int j = 0; j < kStrip; ++j) {
+            const bool live = j >= jlo && j < jhi;
+            lrow[j * (LWP - 1)] = live && m[j] >= 0 ? hv1[j] + m[j] : -1;
+            const int ra = rs1 - B + ia[j];  // row of the maximum's d''
+            nrow1[j * (LWP - 1)] = (AT)(ra >= 0 ? ra : 0);
+            nrow2[j * (LWP - 1)] = csrc[ia[j] * (LW2 - 1)];
+        }
+    }
+    __syncthreads();
+
+    // Level 0: step i on the LDS copy of V_{i+1}, as in the pair's phase 2.
+    int v0[NV0];
+    const int* lcol = &mid[wave * kPairDC][LP + lane];
+#pragma unroll
+    for (int q = 0; q < NV0; ++q) v0[q] = lcol[q * LWP];
+    int m0v[kPairDC], ia0[kPairDC];
+    window_max<B, kPairDC>(v0, m0v, ia0);
+    const RowView aview = row_view(a.a0, a.a_pitch, esz, r2, kPairDC, D);
+    const RowView a1view = row_view(a.a1, a.a_pitch, esz, r2, kPairDC, D);
+    const RowView a2view = row_view(a.a2, a.a_pitch, esz, r2, kPairDC, D);
+    const RowView oview = row_view(a.vout, a.v_pitch, 4, r2, kPairDC, D);
+    const unsigned int op = (unsigned int)a.v_pitch * 4u;
+    const unsigned int ap = (unsigned int)a.a_pitch * (unsigned int)esz;
+    const int jn = col_ok ? min(kPairDC, D - r2) : 0;
+    const int xj = xp - d2;  // x of cell j is xj - j
+    const unsigned int ob = (unsigned int)xj * 4u;
+    const unsigned int ab = (unsigned int)xp * (unsigned int)esz;
+#pragma unroll
+    for (int j = 0; j < kPairDC; ++j) {
+        const bool cell = j < jn;
+        const bool live = cell && (unsigned)(xj - j) < (unsigned)w;
+        const int val = m0v[j] >= 0 ? hv0[j] + m0v[j] : -1;
+        const int ra = r2 - B + ia0[j];
+        const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
+        const unsigned int av1 = nx1[wave * kPairDC + ia0[j]][LP + lane];
+        const unsigned int av2 = nx2[wave * kPairDC + ia0[j]][LP + lane];
+        const unsigned int aoff = cell ? ab + j * ap : kOut;
+        if constexpr (sizeof(AT) == 1) {
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs, (int)aoff, 0, kStoreScope);
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av1, a1view.rs, (int)aoff, 0, kStoreScope);
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av2, a2view.rs, (int)aoff, 0, kStoreScope);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs, (int)aoff, 0, kStoreScope);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av1, a1view.rs, (int)aoff, 0, kStoreScope);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av2, a2view.rs, (int)aoff, 0, kStoreScope);
+        }
+        __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs, (int)(live ? ob + j * (op - 4u) : kOut),
+                                              0, kStoreScope);
+    }
+}
+
 // Step with per-displacement windows [lo(d), hi(d)] (large mode-0 bounds, the
 // angle form, no bound at all).  Both window ends are non-decreasing in d, so
 // the windows of a wave's kDCGeneric displacements fall into groups that
@@ -1194,9 +1467,37 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
         const bool narrow = !a.full && a.win == nullptr && L1 <= 31;
         int i = 1;
         while (i + 1 < k) {
-            if ((i & 1) && i < a.pair_top) {
+            if (i + 2 <= a.tri_top) {
+                // three links made in one launch (see WalkJob::tri_top)
+                const int xn = x + r - (n - 1);
+                if (xn < 0 || xn >= w || r < 0 || r >= D) {
+                    if (lane == 0) *a.score = -1;
+                    return;
+                }
+                const AT* Pi = A + (size_t)(i - 1) * a.a_plane;
+                const unsigned int off = (unsigned int)r * pitch + (unsigned int)xn;
+                const int rn = __builtin_amdgcn_readfirstlane((int)Pi[off]);
+                const int r2 = __builtin_amdgcn_readfirstlane((int)Pi[a.a_plane + off]);
+                const int r3 = __builtin_amdgcn_readfirstlane((int)Pi[2 * a.a_plane + off]);
+                const int xnn = xn + rn - (n - 1);
+                const int x3 = xnn + r2 - (n - 1);
+                if (rn >= D || r2 >= D || xnn < 0 || xnn >= w || x3 < 0 || x3 >= w) {
+                    if (lane == 0) *a.score = -1;
+                    return;
+                }
+                if (lane == 0) {
+                    a.xs[i + 1] = xn;
+                    a.xs[i + 2] = xnn;
+                    a.xs[i + 3] = x3;
+                }
+                x = x3;
+                r = r3;
+                i += 3;
+                continue;
+            }
+            if (i >= a.pair_lo && !((i - a.pair_lo) & 1) && i < a.pair_top) {
                 // a pair of links made in one launch (see WalkJob::pair_top)
-                if (narrow && i + 3 <= a.pair_top) {
+                if (narrow && a.pair_lo == 1 && i + 3 <= a.pair_top) {
                     const bool ok = L1 <= 7    ? walk_four<AT, 4>(a, lane, x, r, i)
                                     : L1 <= 11 ? walk_four<AT, 6>(a, lane, x, r, i)
                                     : L1 <= 17 ? walk_four<AT, 9>(a, lane, x, r, i)
@@ -1328,11 +1629,11 @@ struct DpClass {
     int dc;     // fixed kernels: displacements per thread
     bool a16;
     bool narrow;  // uint16 tables (bands 0 .. k-2)
-    bool pairs;   // two steps per launch allowed (tuning)
-    int stripe;   // item-order stripe of the two-step kernel (tuning)
+    int steps;    // most DP steps per launch allowed, 1..3 (tuning)
+    int stripe;   // item-order stripe of the multi-step kernels (tuning)
     bool operator==(const DpClass& o) const {
         return kind == o.kind && bound == o.bound && dc == o.dc && a16 == o.a16 &&
-               narrow == o.narrow && pairs == o.pairs && stripe == o.stripe;
+               narrow == o.narrow && steps == o.steps && stripe == o.stripe;
     }
 };
 
@@ -1356,7 +1657,7 @@ DpClass class_of(const DpJobSpec& j) {
     c.dc = fixed ? j.plan.dc : kDCGeneric;
     c.a16 = j.plan.a16;
     c.narrow = j.tables.narrow > 0;
-    c.pairs = j.plan.pairs;
+    c.steps = j.plan.steps;
     c.stripe = j.plan.stripe;
     if (!fixed) c.kind = (int)WindowKind::Generic;  // one scanning kernel for every other kind
     return c;
@@ -1506,6 +1807,27 @@ hipError_t launch_pair(int bound, bool pinned, bool narrow, hipStream_t s, int g
                   : launch_pair_t<AT, CAP, int32_t>(bound, pinned, s, grid, pk);
 }
 
+template <typename AT, int CAP, typename TT>
+hipError_t launch_triple_t(int bound, hipStream_t s, int grid, const DpTriplePack<CAP>& pk) {
+#define FHTP_B(BB)                                                                         \
+    case BB:                                                                               \
+        hipLaunchKernelGGL((dp_triple_fixed<BB, AT, CAP, TT>), dim3(grid),                 \
+                           dim3(64 * kPairWaves), 0, s, pk);                               \
+        return hipSuccess;
+    switch (bound) {
+        FHTP_B(0) FHTP_B(1) FHTP_B(2) FHTP_B(3) FHTP_B(4) FHTP_B(5) FHTP_B(6) FHTP_B(7) FHTP_B(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef FHTP_B
+}
+
+template <typename AT, int CAP>
+hipError_t launch_triple(int bound, bool narrow, hipStream_t s, int grid,
+                         const DpTriplePack<CAP>& pk) {
+    return narrow ? launch_triple_t<AT, CAP, uint16_t>(bound, s, grid, pk)
+                  : launch_triple_t<AT, CAP, int32_t>(bound, s, grid, pk);
+}
+
 // Two steps per launch need the fixed window, the 8-displacement chunk (an
 // image whose step grid leaves the chip latency-bound on its own) and byte
 // offsets inside a workgroup's rows that fit 32 bits.
@@ -1513,32 +1835,45 @@ bool pairs_apply(const DpJobSpec& J) {
     const Geometry& g = J.g;
     const long long rows = kPairRows + 4LL * kMaxFixedB + kStrip;  // the widest view
     const long long pitch = std::max(g.W, g.pitch);
-    return J.plan.pairs && J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC &&
+    return J.plan.steps >= 2 && J.plan.kind == WindowKind::Fixed && J.plan.dc == kPairDC &&
            g.k >= 2 && rows * pitch * 4 < 0x7fffffffLL;
 }
 
-// Steps of a pack of images of one class with bands k-2 .. 1 taken two per
-// launch, then the last step.  Images are aligned at the end: every image's
-// last step is in the final launch and its pairs in the launches just before
-// it; an image with an odd count of bands before the last step does its top
-// band alone in one launch ahead of all pairs.  Per image, the launches that
-// make V alternate between its two value planes so that V_1 lands in plane 1,
-// where the last step reads it; a launch never writes the plane it reads, and
-// an image that sits out a launch leaves its planes untouched.
+// Three steps per launch: as two, with a bound of at most kTriMaxB and no pin.
+bool triples_apply(const DpJobSpec& J) {
+    return pairs_apply(J) && J.plan.steps >= 3 && J.plan.bound <= kTriMaxB && J.pin.j < 0;
+}
+
+// Steps of a pack of images of one class with bands k-2 .. 1 taken G = 2 or
+// 3 per launch, then the last step.  Images are aligned at the end: every
+// image's last step is in the final launch and its groups in the launches
+// just before it.  The P = k-2 bands before the last step make P / G groups;
+// the P % G top bands left over go ahead of all groups: one band alone in a
+// one-step launch, two (G = 3) as a pair in a two-step launch.  Per image,
+// the launches that make V alternate between its two value planes so that
+// V_1 lands in plane 1, where the last step reads it; a launch never writes
+// the plane it reads, and an image that sits out a launch leaves its planes
+// untouched.
 template <typename AT, int CAP>
-hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*>& jobs,
-                            hipStream_t s) {
-    int Q = 0;  // pair launches
-    bool singles = false;
+hipError_t run_steps_grouped(const DpClass& c, int G, const std::vector<const DpJobSpec*>& jobs,
+                             hipStream_t s) {
+    int Q = 0;  // group launches
+    bool singles = false, head_pairs = false;
     for (const DpJobSpec* J : jobs) {
-        Q = std::max(Q, (J->g.k - 2) / 2);
-        singles = singles || ((J->g.k - 2) & 1);
+        const int P = J->g.k - 2;
+        Q = std::max(Q, P / G);
+        singles = singles || P % G == 1;
+        head_pairs = head_pairs || P % G == 2;
     }
+    // V-launches of an image: the head (if any), then its groups.
+    auto vlaunches = [G](const DpJobSpec& J) {
+        const int P = J.g.k - 2;
+        return (P % G ? 1 : 0) + P / G;
+    };
     // Input plane of V-launch j of an image (j = 0: the table H_{k-1}) and its
     // output plane.
-    auto plane_of = [](const DpJobSpec& J, int j) {
-        const int P = J.g.k - 2;
-        const int m = (P & 1) + P / 2;  // V-launches of the image
+    auto plane_of = [&](const DpJobSpec& J, int j) {
+        const int m = vlaunches(J);
         return J.buf.vplanes + (size_t)(((m - 1 - j) & 1) ? 0 : 1) * ((size_t)J.g.D * J.g.pitch);
     };
     auto input_of = [&](const DpJobSpec& J, int j, const int32_t*& vin, int& pitch) {
@@ -1556,7 +1891,7 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
         int cnt = 0;
         for (const DpJobSpec* J : jobs) {
             const Geometry& g = J->g;
-            if (!((g.k - 2) & 1)) continue;
+            if ((g.k - 2) % G != 1) continue;
             const int i = g.k - 2;  // its top band
             DpJob a = base_job(*J);
             input_of(*J, 0, a.vin, a.vin_pitch);
@@ -1577,48 +1912,111 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
         hipError_t e = launch_step<AT, CAP>(c, s, pk);
         if (e != hipSuccess) return e;
     }
-    // one timing bracket around the whole run of pair launches
-    TimedLaunch tl_pairs(Q > 0 ? "dp_pair_fixed" : nullptr, s, Q);
-    for (int L = 0; L < Q; ++L) {
-        DpPairPack<CAP> pk{};
-        long long total = 0;
-        int cnt = 0;
-        for (const DpJobSpec* J : jobs) {
-            const Geometry& g = J->g;
-            const int P = g.k - 2, np = P / 2, odd = P & 1;
-            const int t = L - (Q - np);  // the image's pair index in this launch
-            if (t < 0) continue;
-            const int i = P - odd - 2 * t;  // phase-1 band; phase 2 makes band i-1
-            const size_t plane = (size_t)g.D * g.pitch;
-            AT* A = static_cast<AT*>(J->buf.a);
-            DpPairJob a{};
-            input_of(*J, odd + t, a.vin, a.vin_pitch);
-            if (odd + t == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);  // vin is H_{k-1}
-            a.pin1_x = J->pin.j == i ? J->pin.x : -1;
-            a.pin0_x = J->pin.j == i - 1 ? J->pin.x : -1;
-            a.h1 = band_table(*J, i);
-            a.h0 = band_table(*J, i - 1);
-            a.vout = plane_of(*J, odd + t);
-            a.a1 = A + (size_t)(i - 1) * plane;  // A_{i+1}
-            a.a0 = A + (size_t)(i - 2) * plane;  // A_i
-            a.h_pitch = g.W;
-            a.v_pitch = g.pitch;
-            a.a_pitch = g.pitch;
-            a.n = g.n;
-            a.w = g.w;
-            a.items_x = (g.w + 63) / 64;
-            a.items_y = (g.D + kPairRows - 1) / kPairRows;
-            a.item0 = (int)total;
-            total += (long long)a.items_x * a.items_y;
-            if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-            pk.job[cnt++] = a;
-        }
+    // A pair launch: image J's pair with phase-1 band i, as its V-launch j.
+    auto pair_job = [&](const DpJobSpec& J, int i, int j, DpPairJob& a) {
+        const Geometry& g = J.g;
+        const size_t plane = (size_t)g.D * g.pitch;
+        AT* A = static_cast<AT*>(J.buf.a);
+        a = DpPairJob{};
+        input_of(J, j, a.vin, a.vin_pitch);
+        if (j == 0) first_step_pin(J, a.vin_pin, a.vin_pin_x);  // vin is H_{k-1}
+        a.pin1_x = J.pin.j == i ? J.pin.x : -1;
+        a.pin0_x = J.pin.j == i - 1 ? J.pin.x : -1;
+        a.h1 = band_table(J, i);
+        a.h0 = band_table(J, i - 1);
+        a.vout = plane_of(J, j);
+        a.a1 = A + (size_t)(i - 1) * plane;  // A_{i+1}
+        a.a0 = A + (size_t)(i - 2) * plane;  // A_i
+        a.h_pitch = g.W;
+        a.v_pitch = g.pitch;
+        a.a_pitch = g.pitch;
+        a.n = g.n;
+        a.w = g.w;
+        a.items_x = (g.w + 63) / 64;
+        a.items_y = (g.D + kPairRows - 1) / kPairRows;
+    };
+    auto launch_pairs = [&](DpPairPack<CAP>& pk, int cnt, long long total) {
         pk.count = cnt;
         pk.stripe = std::max(1, c.stripe);
         bool pinned = false;
         for (int q = 0; q < cnt; ++q)
             pinned = pinned || pk.job[q].vin_pin != 0 || pk.job[q].pin1_x >= 0 || pk.job[q].pin0_x >= 0;
-        hipError_t e = launch_pair<AT, CAP>(jobs[0]->plan.bound, pinned, c.narrow, s, (int)total, pk);
+        return launch_pair<AT, CAP>(jobs[0]->plan.bound, pinned, c.narrow, s, (int)total, pk);
+    };
+    if (head_pairs) {  // G = 3: two top bands left over
+        DpPairPack<CAP> pk{};
+        long long total = 0;
+        int cnt = 0;
+        for (const DpJobSpec* J : jobs) {
+            if ((J->g.k - 2) % G != 2) continue;
+            DpPairJob a;
+            pair_job(*J, J->g.k - 2, 0, a);
+            a.item0 = (int)total;
+            total += (long long)a.items_x * a.items_y;
+            if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            pk.job[cnt++] = a;
+        }
+        TimedLaunch tl("dp_pair_fixed", s);
+        hipError_t e = launch_pairs(pk, cnt, total);
+        if (e != hipSuccess) return e;
+    }
+    // one timing bracket around the whole run of group launches
+    TimedLaunch tl_groups(Q > 0 ? (G == 3 ? "dp_triple_fixed" : "dp_pair_fixed") : nullptr, s, Q);
+    for (int L = 0; L < Q; ++L) {
+        long long total = 0;
+        int cnt = 0;
+        hipError_t e;
+        if (G == 2) {
+            DpPairPack<CAP> pk{};
+            for (const DpJobSpec* J : jobs) {
+                const int P = J->g.k - 2, np = P / 2, odd = P & 1;
+                const int t = L - (Q - np);  // the image's pair index in this launch
+                if (t < 0) continue;
+                DpPairJob a;
+                pair_job(*J, P - odd - 2 * t, odd + t, a);  // phase 2 makes the band below
+                a.item0 = (int)total;
+                total += (long long)a.items_x * a.items_y;
+                if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+                pk.job[cnt++] = a;
+            }
+            e = launch_pairs(pk, cnt, total);
+        } else {
+            DpTriplePack<CAP> pk{};
+            for (const DpJobSpec* J : jobs) {
+                const Geometry& g = J->g;
+                const int P = g.k - 2, nt = P / 3, rem = P % 3;
+                const int t = L - (Q - nt);  // the image's triple index in this launch
+                if (t < 0) continue;
+                const int i = P - rem - 3 * t - 2;  // level-0 band; levels 1, 2 make i+1, i+2
+                const int j = (rem ? 1 : 0) + t;
+                const size_t plane = (size_t)g.D * g.pitch;
+                AT* A = static_cast<AT*>(J->buf.a);
+                DpTripleJob a{};
+                input_of(*J, j, a.vin, a.vin_pitch);
+                a.h2 = band_table(*J, i + 2);
+                a.h1 = band_table(*J, i + 1);
+                a.h0 = band_table(*J, i);
+                a.vout = plane_of(*J, j);
+                a.a0 = A + (size_t)(i - 1) * plane;  // A_{i+1}
+                a.a1 = A + (size_t)i * plane;        // A_{i+2}
+                a.a2 = A + (size_t)(i + 1) * plane;  // A_{i+3}
+                a.vin_pitch = j == 0 ? g.W : g.pitch;
+                a.h_pitch = g.W;
+                a.v_pitch = g.pitch;
+                a.a_pitch = g.pitch;
+                a.n = g.n;
+                a.w = g.w;
+                a.items_x = (g.w + 63) / 64;
+                a.items_y = (g.D + kPairRows - 1) / kPairRows;
+                a.item0 = (int)total;
+                total += (long long)a.items_x * a.items_y;
+                if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+                pk.job[cnt++] = a;
+            }
+            pk.count = cnt;
+            pk.stripe = std::max(1, c.stripe);
+            e = launch_triple<AT, CAP>(jobs[0]->plan.bound, c.narrow, s, (int)total, pk);
+        }
         if (e != hipSuccess) return e;
     }
     // last step of every image: V_1 (or the table H_1 when k = 2) to the keys
@@ -1627,8 +2025,7 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
     int cnt = 0;
     for (const DpJobSpec* J : jobs) {
         const Geometry& g = J->g;
-        const int P = g.k - 2;
-        const int m = (P & 1) + P / 2;
+        const int m = vlaunches(*J);
         DpJob a = base_job(*J);
         input_of(*J, m, a.vin, a.vin_pitch);
         if (m == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);  // k = 2: vin is H_1
@@ -1644,14 +2041,14 @@ hipError_t run_steps_paired(const DpClass& c, const std::vector<const DpJobSpec*
     }
     pk.count = cnt;
     pk.total = (int)total;
-    tl_pairs.close();
+    tl_groups.close();
     TimedLaunch tl(step_family(c), s);
     return launch_step<AT, CAP>(c, s, pk);
 }
 
 template <typename AT, int CAP>
 hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs,
-                     const std::vector<const DpJobSpec*>& paired, hipStream_t s) {
+                     const std::vector<std::pair<const DpJobSpec*, int>>& grouped, hipStream_t s) {
     for (size_t q0 = 0; q0 < jobs.size(); q0 += CAP) {
         WalkPack<CAP> pk{};
         const int cnt = (int)std::min<size_t>(CAP, jobs.size() - q0);
@@ -1675,9 +2072,16 @@ hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs,
             a.win = J.plan.kind == WindowKind::Angle ? J.buf.win : nullptr;
             a.score = J.score;
             a.xs = J.xs;
-            // run_steps_paired makes bands 1 .. P - (P & 1) in pairs, P = k - 2
-            const bool in_pairs = std::find(paired.begin(), paired.end(), &J) != paired.end();
-            a.pair_top = in_pairs ? (g.k - 2) - ((g.k - 2) & 1) : 0;
+            // run_steps_grouped with G = 2 makes bands 1 .. P - (P & 1) in
+            // pairs, P = k - 2; with G = 3 bands 1 .. 3(P / 3) in triples and,
+            // when two bands are left over, those two as a pair
+            int G = 1;
+            for (const auto& e : grouped)
+                if (e.first == &J) G = e.second;
+            const int P = g.k - 2;
+            a.tri_top = G == 3 ? 3 * (P / 3) : 0;
+            a.pair_lo = G == 3 ? a.tri_top + 1 : 1;
+            a.pair_top = G == 2 ? P - (P & 1) : G == 3 && P % 3 == 2 ? P : 0;
         }
         pk.count = cnt;
         {
@@ -1723,7 +2127,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
     for (const DpJobSpec* J : jobs)
         if (J->g.k >= 2) rest.push_back(J);
     std::vector<bool> done(rest.size(), false);
-    std::vector<const DpJobSpec*> paired_jobs;  // images whose steps went two per launch
+    std::vector<std::pair<const DpJobSpec*, int>> grouped;  // images whose steps went G per launch
     for (size_t q = 0; q < rest.size(); ++q) {
         if (done[q]) continue;
         const DpClass c = class_of(*rest[q]);
@@ -1736,19 +2140,24 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
         for (size_t q0 = 0; q0 < group.size(); q0 += CAP) {
             std::vector<const DpJobSpec*> pack(group.begin() + q0,
                                                group.begin() + std::min(group.size(), q0 + CAP));
-            bool paired = false;  // every image qualifies and one has a pair of steps
-            bool all = true;
+            // G steps per launch when every image qualifies and one has a
+            // group of G steps
+            bool all2 = true, all3 = true;
+            int kmax = 0;
             for (const DpJobSpec* J : pack) {
-                all = all && pairs_apply(*J) && (CAP == 1 || J->pin.j < 0);
-                paired = paired || J->g.k >= 4;
+                all2 = all2 && pairs_apply(*J) && (CAP == 1 || J->pin.j < 0);
+                all3 = all3 && triples_apply(*J);
+                kmax = std::max(kmax, J->g.k);
             }
-            hipError_t e = all && paired ? run_steps_paired<AT, CAP>(c, pack, s)
-                                         : run_steps<AT, CAP>(c, pack, s);
+            const int G = all3 && kmax >= 5 ? 3 : all2 && kmax >= 4 ? 2 : 1;
+            hipError_t e = G > 1 ? run_steps_grouped<AT, CAP>(c, G, pack, s)
+                                 : run_steps<AT, CAP>(c, pack, s);
             if (e != hipSuccess) return e;
-            if (all && paired) paired_jobs.insert(paired_jobs.end(), pack.begin(), pack.end());
+            if (G > 1)
+                for (const DpJobSpec* J : pack) grouped.emplace_back(J, G);
         }
     }
-    return run_walks<AT, CAP>(jobs, paired_jobs, s);
+    return run_walks<AT, CAP>(jobs, grouped, s);
 }
 
 }  // namespace

@@ -89,8 +89,8 @@ struct DpPlan {
     double tan_gamma;   // mode 1
     bool a16;           // back-pointers stored as uint16 (D > 256) instead of uint8
     int dc;             // displacements per thread in the fixed-window step (8 or 16)
-    bool pairs = true;  // two steps per launch where the window allows it
-    int stripe = 16;    // column tiles per stripe of the two-step kernel's item order
+    int steps = 2;      // most DP steps per launch (1..3) where the window allows them
+    int stripe = 16;    // column tiles per stripe of the multi-step kernels' item order
     int fht_grid = 0;   // the detection's FHT: 0 resident grid, 1 one workgroup per item
 };
 

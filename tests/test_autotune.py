@@ -20,7 +20,7 @@ def clean_rules():
 
 
 def test_rules_round_trip_and_clear():
-    rules = [autotune.rule(dtype=0, log2n=6, window=0, dc=8, pairs=1, stripe=8, fht_grid=1),
+    rules = [autotune.rule(dtype=0, log2n=6, window=0, dc=8, steps=2, stripe=8, fht_grid=1),
              autotune.rule(window=1, fht_grid=0, w_min=10, w_max=99)]
     fhtp.tune_set(rules)
     assert fhtp.tune_get() == rules
@@ -28,11 +28,11 @@ def test_rules_round_trip_and_clear():
     assert fhtp.tune_get() == []
 
 
-@pytest.mark.parametrize("bad", [dict(dc=12), dict(pairs=2), dict(stripe=65), dict(stripe=-1),
+@pytest.mark.parametrize("bad", [dict(dc=12), dict(steps=4), dict(steps=-1), dict(stripe=65), dict(stripe=-1),
                                  dict(fht_grid=2), dict(window=2), dict(dtype=3), dict(log2n=11),
                                  dict(w_min=5, w_max=4), dict(w_min=-1)])
 def test_out_of_range_rules_are_refused_and_change_nothing(bad):
-    good = autotune.rule(window=0, dc=16, pairs=0)
+    good = autotune.rule(window=0, dc=16, steps=1)
     fhtp.tune_set([good])
     with pytest.raises(fhtp.FhtpError) as e:
         fhtp.tune_set([autotune.rule(), dict(autotune.rule(), **bad)])
@@ -48,7 +48,7 @@ def test_rule_count_limit():
 
 
 def test_rules_for_groups_cover_both_window_kinds_then_a_catch_all():
-    dp = dict(dc=8, pairs=1, stripe=4)
+    dp = dict(dc=8, steps=3, stripe=4)
     rules = autotune._rules_for([(0, 6), (1, 7)], dp, {(1, 7): 1})
     assert len(rules) == 5
     assert rules[0] == autotune.rule(dtype=0, log2n=6, window=0, fht_grid=0, **dp)
@@ -61,9 +61,9 @@ def test_rules_for_groups_cover_both_window_kinds_then_a_catch_all():
 def test_saved_plan_loads_only_on_the_same_device_and_library(tmp_path, monkeypatch):
     key = {"device": "MI355X", "arch": "gfx950", "library": fhtp.version()}
     monkeypatch.setattr(autotune, "device_key", lambda: dict(key))
-    res = autotune.TuneResult(rules=autotune._rules_for([(0, 5)], dict(dc=16, pairs=0, stripe=0),
+    res = autotune.TuneResult(rules=autotune._rules_for([(0, 5)], dict(dc=16, steps=1, stripe=0),
                                                         {(0, 5): 1}),
-                              default_ms=2.0, tuned_ms=1.5, dp_choice=dict(dc=16, pairs=0, stripe=0),
+                              default_ms=2.0, tuned_ms=1.5, dp_choice=dict(dc=16, steps=1, stripe=0),
                               fht_choice={"dtype0 log2n5": 1})
     path = str(tmp_path / "plan.json")
     autotune.save(res, path, workload="test")
@@ -96,7 +96,7 @@ def test_tuner_logic_with_a_simulated_workload(monkeypatch):
             if not rules:
                 return 10.0
             dp = rules[0]
-            t = 5.0 + (0 if (dp["pairs"], dp["stripe"]) == (1, 8) else 1.0)
+            t = 5.0 + (0 if (dp["steps"], dp["stripe"]) == (2, 8) else 1.0)
             t -= 0.5 * sum(r["fht_grid"] for r in rules if r["window"] == 0 and r["log2n"] == 7)
             costs[len(costs)] = t
             return t
@@ -109,7 +109,7 @@ def test_tuner_logic_with_a_simulated_workload(monkeypatch):
     fhtp.tune_set(before)
     res = autotune.tune([None], [1], install_result=False)
     assert fhtp.tune_get() == before
-    assert res.dp_choice == dict(dc=8, pairs=1, stripe=8)
+    assert res.dp_choice == dict(dc=8, steps=2, stripe=8)
     assert res.fht_choice == {"dtype0 log2n5": 0, "dtype1 log2n7": 1}
     assert res.default_ms == 10.0 and res.tuned_ms == 4.5
     assert res.rules == autotune._rules_for([(0, 5), (1, 7)], res.dp_choice, {(0, 5): 0, (1, 7): 1})

@@ -1,0 +1,124 @@
+"""GPU parity of the multi-step DP launches: one, two and three steps per launch.
+
+Fixed windows take up to two DP steps per launch by default, and up to three
+when a tuning rule asks for it (bounds of at most 8 shifts, no through-point
+pin; else two).  Each case is run
+with the steps per launch forced to 1, 2 and 3 by a tuning rule and must give
+the oracle's score and vertices exactly.  The shapes cover every remainder of
+the k-2 bands before the last step modulo 3 (no head launch, a one-step head,
+a two-step head), ragged widths, band heights from 8 to 256 rows (16-bit
+back-pointers), windows wider than the displacement range, 8- and 16-bit
+pixels (uint16 and int32 tables), and batches whose images have different
+band counts, so that images sit out the first launches.
+"""
+
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection, outside per-test time limits)
+
+from tests.gpu_util import announce, host, require_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    # (h, w, k, pixel type)
+    (32 * 5, 333, 5, np.uint8),      # n = 32: k-2 = 3, one triple
+    (64 * 6, 200, 6, np.uint8),      # n = 64: k-2 = 4, a one-step head, one triple
+    (16 * 7, 70, 7, np.uint16),      # n = 16: k-2 = 5, a two-step head, one triple
+    (128 * 8, 130, 8, np.uint8),     # n = 128: 255 displacements, k-2 = 6, two triples
+    (8 * 12, 65, 12, np.uint8),      # n = 8: windows wider than the displacement range
+    (256 * 5, 300, 5, np.uint8),     # n = 256: 16-bit back-pointers, uint16 tables
+    (64 * 11, 517, 11, np.uint16),   # k-2 = 9: three triples, int32 tables
+    (4 * 9, 40, 9, np.uint8),        # n = 4: 7 displacements
+    (32 * 3, 90, 3, np.uint8),       # k-2 = 1: only the head
+    (32 * 4, 90, 4, np.uint8),       # k-2 = 2: only the head pair
+]
+
+
+def _img(h, w, dtype, seed):
+    rng = np.random.default_rng([191201884, 141, seed])
+    top = 255 if dtype == np.uint8 else 9000
+    img = rng.integers(0, top + 1, size=(h, w)).astype(dtype)
+    if seed % 3 == 0:
+        img //= 64  # tie-heavy
+    return img
+
+
+def _steps_rule(steps):
+    from paper_1912_01884_amd import autotune
+    return [autotune.rule(window=0, dc=8, steps=steps)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1912_01884_amd import fhtp
+    return fhtp
+
+
+@pytest.mark.parametrize("B", [0, 1, 2, 5, 8, 9, 16])
+@pytest.mark.parametrize("h,w,k,dt", SHAPES, ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in SHAPES])
+def test_steps_per_launch(dev, F, orc, h, w, k, dt, B):
+    from paper_1912_01884_amd import fhtp
+    img = _img(h, w, dt, 17 * h + w + B)
+    want_s, want_x = orc.detect_polyline(img, k, bend=B)
+    d = to_device(img, dev)
+    try:
+        for steps in (3, 2, 1):
+            fhtp.tune_set(_steps_rule(steps))
+            announce(f"steps per launch {steps}: {h}x{w} k={k} B={B}")
+            sc, xs = F.detect_polyline(d, k, bend=B)
+            assert int(host(sc)[0]) == want_s, steps
+            assert host(xs).tolist() == want_x.tolist(), steps
+    finally:
+        fhtp.tune_set([])
+
+
+def test_steps_in_batches(dev, F, orc):
+    """One pack with k from 2 to 13 (every head kind and up to 3 triples),
+    mixed band heights and pixel types, one bound class per call."""
+    from paper_1912_01884_amd import fhtp
+    rng = np.random.default_rng([191201884, 142])
+    for B in (1, 4, 8):
+        imgs, ks = [], []
+        for k in range(2, 14):
+            n = int(rng.choice([8, 16, 32, 64]))
+            w = int(rng.integers(40, 400))
+            dt = np.uint8 if k % 2 else np.uint16
+            imgs.append(_img(n * k, w, dt, 1000 * B + k))
+            ks.append(k)
+        want = [orc.detect_polyline(im, k, bend=B) for im, k in zip(imgs, ks)]
+        dimgs = [to_device(im, dev) for im in imgs]
+        try:
+            for steps in (3, 2):
+                fhtp.tune_set(_steps_rule(steps))
+                announce(f"batch of {len(imgs)}, steps per launch {steps}, B={B}")
+                out = F.detect_batch(dimgs, ks, bends=[B] * len(ks))
+                for q, (s, x) in enumerate(want):
+                    assert int(host(out[q][0])[0]) == s, (steps, q)
+                    assert host(out[q][1]).tolist() == x.tolist(), (steps, q)
+        finally:
+            fhtp.tune_set([])
+
+
+@pytest.mark.parametrize("j", [0, 3, 5, 8])
+def test_pinned_queries_take_pairs(dev, F, orc, j):
+    """Through-point queries keep two steps per launch when three are asked
+    for (the pin masks live in the two-step kernel)."""
+    from paper_1912_01884_amd import fhtp
+    h, w, k = 64 * 8, 300, 8
+    img = _img(h, w, np.uint8, 555 + j)
+    x = 37 + 11 * j
+    want_s, want_x = orc.detect_through_point(img, k, j, x, bend=4)
+    fhtp.tune_set(_steps_rule(3))
+    try:
+        announce(f"pinned query j={j} x={x} with three steps per launch asked for")
+        sc, xs = F.detect_polyline_ex(to_device(img, dev), k, bend=4, pin=(j, x))
+    finally:
+        fhtp.tune_set([])
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()

@@ -48,7 +48,7 @@ def _cands():
 
 
 @pytest.mark.parametrize("dp,fg", _cands(),
-                         ids=[f"dc{d['dc']}p{d['pairs']}s{d['stripe']}g{g}" for d, g in _cands()])
+                         ids=[f"dc{d['dc']}t{d['steps']}s{d['stripe']}g{g}" for d, g in _cands()])
 def test_every_candidate_matches_the_oracle(case, dp, fg):
     from paper_1912_01884_amd import autotune, fhtp
     dev, jobs, want = case
