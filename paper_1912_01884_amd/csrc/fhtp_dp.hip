@@ -1619,6 +1619,242 @@ __global__ void angle_windows(int n, double t, int32_t* __restrict__ win) {
     win[D + r] = hi;
 }
 
+// ---- unbounded bend: the column-maximum recurrence ---------------------------
+//
+// With every bend admissible (no restriction of Section 2.3), the range
+// maximum of eq. (3) runs over every d', so the best continuation
+// M_{i+1}(x', d) = max_{d'} V_{i+1}(x', d') does not depend on d.  Writing
+// U_i(x) for that column maximum of V_i,
+//
+//   U_i(x) = max over d with x + d in [0, w) of H_i(x, d) + U_{i+1}(x + d),
+//
+// with U_k = 0 (V_{k-1} is the table wherever x + d stays in the image), and
+// the back-pointer A_{i+1}(x', d) is the same for every d: the smallest d'
+// reaching U_{i+1}(x').  So a step keeps one value and one back-pointer per
+// column, B_i(x) = that smallest d (as its row d + n - 1), instead of the
+// planes of V_i and A_{i+1}: it reads the table once and U_{i+1} (w values,
+// from cache) and writes 5 bytes per column.  The last step (band 0) reduces
+// U_0 to one packed key per workgroup (largest value, then smallest x); the
+// walk takes x_0 from the keys and follows x_{i+1} = x_i + d_i with
+// d_i = B_i(x_i).  The greedy smallest index at every step gives the
+// lexicographically smallest optimal polyline, as in the other kernels.
+//
+// Layout: a workgroup owns 64 columns x (one per lane, coalesced loads) and
+// its kColWaves waves split the displacement rows, each scanning its rows in
+// ascending order; the waves' partial maxima meet in LDS, lowest rows first.
+constexpr int kColWaves = 16;
+
+struct ColJob {
+    const void* htab;         // H_i (the kernel's TT; int32 for band k-1)
+    const int32_t* uin;       // U_{i+1}, or null on band k-1 (U_k = 0)
+    int32_t* uout;            // U_i, or null on band 0
+    void* bout;               // B_i: the row of each column's smallest maximizing d
+    unsigned long long* key;  // band 0: one packed key per workgroup, else null
+    int h_pitch;
+    int n, w;
+    int item0;  // first workgroup of this image in the launch
+};
+
+template <int CAP>
+struct ColPack {
+    ColJob job[CAP];
+    int count;
+};
+
+__device__ __forceinline__ unsigned long long col_key(int val, int x) {
+    return ((unsigned long long)(unsigned int)(val + 1) << 32) |
+           (unsigned long long)(0xffffffffu - (unsigned int)x);
+}
+
+template <typename AT, int CAP, typename TT>
+__global__ __launch_bounds__(64 * kColWaves) void dp_colmax(ColPack<CAP> pk) {
+    const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);
+    int jj = 0;
+    if constexpr (CAP > 1) {
+        int hi = pk.count - 1;
+        while (jj < hi) {
+            const int md = (jj + hi + 1) >> 1;
+            if (pk.job[md].item0 <= it)
+                jj = md;
+            else
+                hi = md - 1;
+        }
+    }
+    const ColJob& a = pk.job[jj];
+    const int n = a.n, w = a.w, D = 2 * n - 1;
+    const int tile = CAP > 1 ? it - a.item0 : it;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int x = tile * 64 + lane;
+    const bool col = x < w;
+    const int R = (D + kColWaves - 1) / kColWaves;
+    const int r0 = wave * R, r1 = min(r0 + R, D);
+    const TT* H = static_cast<const TT*>(a.htab);
+    int best = kEmpty, brow = 0;
+    for (int rb = r0; rb < r1; rb += 8) {
+        int hv[8], uv[8];
+        bool ok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int r = rb + j;
+            const int xt = x + r - (n - 1);  // successor column x + d
+            ok[j] = col && r < r1 && (unsigned)xt < (unsigned)w;
+            const size_t off = ok[j] ? (size_t)r * (size_t)a.h_pitch + (size_t)x : 0;
+            hv[j] = (int)H[off];
+            uv[j] = a.uin ? a.uin[ok[j] ? xt : 0] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int v = hv[j] + uv[j];
+            const bool t = ok[j] && v > best;  // ascending rows: ties keep the smaller d
+            best = t ? v : best;
+            brow = t ? rb + j : brow;
+        }
+    }
+    __shared__ int pv[kColWaves][64];
+    __shared__ int pr[kColWaves][64];
+    pv[wave][lane] = best;
+    pr[wave][lane] = brow;
+    __syncthreads();
+    if (wave != 0) return;
+    // waves hold ascending row ranges: a later wave wins only when larger
+    int b = pv[0][lane], r = pr[0][lane];
+#pragma unroll
+    for (int q = 1; q < kColWaves; ++q) {
+        const bool t = pv[q][lane] > b;
+        b = t ? pv[q][lane] : b;
+        r = t ? pr[q][lane] : r;
+    }
+    if (col) {
+        static_cast<AT*>(a.bout)[x] = (AT)r;
+        if (a.uout) a.uout[x] = b;
+    }
+    if (a.key) {
+        const unsigned long long kk = wave_max_u64(col ? col_key(b, x) : 0ull);
+        if (lane == 0) a.key[tile] = kk;
+    }
+}
+
+// Walk of the column recurrence, one wave per image: x_0 from the keys, then
+// d_i = B_i(x_i), several bands per memory round trip: with x_i known, a trip
+// loads B_i(x_i), B_{i+1} at every column x_i + d the first link can reach
+// (U1 per lane) and, when U2 > 0, B_{i+2} at every column x_i + s the first
+// two can reach (U2 per lane), and resolves three bands (two when U2 = 0)
+// with lane reads.  Loads are clamped into the rows and the image; what an
+// unused candidate reads is never used.
+struct ColWalkJob {
+    const unsigned long long* key;
+    const void* b_base;  // row i holds B_i, i = 0 .. k-1
+    int32_t* score;
+    int32_t* xs;
+    int b_pitch, n_keys;
+    int n, w, k;
+};
+
+template <int CAP>
+struct ColWalkPack {
+    ColWalkJob job[CAP];
+    int count;
+};
+
+template <typename AT, int U1, int U2>
+__device__ __forceinline__ bool colwalk_trip(const ColWalkJob& a, int lane, int& x, int& i) {
+    const int n = a.n, w = a.w, k = a.k, D = 2 * n - 1;
+    const AT* B = static_cast<const AT*>(a.b_base);
+    const size_t pitch = (size_t)a.b_pitch;
+    const int i1 = min(i + 1, k - 1), i2 = min(i + 2, k - 1);
+    const int c0v = B[(size_t)i * pitch + (size_t)x];
+    int c1[U1], c2[U2 > 0 ? U2 : 1];
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+        const int xc = min(max(x + lane + 64 * u - (n - 1), 0), w - 1);
+        c1[u] = B[(size_t)i1 * pitch + (size_t)xc];
+    }
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+        const int xc = min(max(x + lane + 64 * u - 2 * (n - 1), 0), w - 1);
+        c2[u] = B[(size_t)i2 * pitch + (size_t)xc];
+    }
+    // no branch until every load of the trip has been used
+    const int r0 = __builtin_amdgcn_readfirstlane(c0v);
+    const int x1 = x + r0 - (n - 1);
+    bool ok = r0 < D && (unsigned)x1 < (unsigned)w;
+    int q = r0;  // candidate index of the second link's column: d_i + n - 1
+    int m1 = c1[0];
+#pragma unroll
+    for (int u = 1; u < U1; ++u) m1 = (q >> 6) == u ? c1[u] : m1;
+    const int r1 = __builtin_amdgcn_readlane(m1, q & 63);
+    const int x2 = x1 + r1 - (n - 1);
+    const bool two = i + 1 < k;
+    const bool ok2 = ok && two && r1 < D && (unsigned)x2 < (unsigned)w;
+    int r2 = 0, x3 = 0;
+    bool ok3 = false;
+    const bool three = U2 > 0 && i + 2 < k;
+    if constexpr (U2 > 0) {
+        const int q2 = r0 + r1;  // (x2 - x) + 2(n - 1)
+        int m2 = c2[0];
+#pragma unroll
+        for (int u = 1; u < U2; ++u) m2 = (q2 >> 6) == u ? c2[u] : m2;
+        r2 = __builtin_amdgcn_readlane(m2, q2 & 63);
+        x3 = x2 + r2 - (n - 1);
+        ok3 = ok2 && three && r2 < D && (unsigned)x3 < (unsigned)w;
+    }
+    if (lane == 0) {
+        if (ok) a.xs[i + 1] = x1;
+        if (ok2) a.xs[i + 2] = x2;
+        if (ok3) a.xs[i + 3] = x3;
+    }
+    if (!ok || (two && !ok2) || (three && !ok3)) return false;
+    if (three) {
+        x = x3;
+        i += 3;
+    } else if (two) {
+        x = x2;
+        i += 2;
+    } else {
+        x = x1;
+        i += 1;
+    }
+    return true;
+}
+
+template <typename AT, int CAP>
+__global__ __launch_bounds__(64) void walk_colmax(ColWalkPack<CAP> pk) {
+    const ColWalkJob& a = pk.job[blockIdx.x];
+    const int lane = threadIdx.x;
+    unsigned long long m = 0;
+    for (int q0 = 0; q0 < a.n_keys; q0 += 64 * 8) {
+        unsigned long long t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 64 + lane;
+            t[u] = q < a.n_keys ? a.key[q] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m = t[u] > m ? t[u] : m;
+    }
+    m = wave_max_u64(m);
+    const unsigned int xu = 0xffffffffu - (unsigned int)(m & 0xffffffffull);
+    if ((m >> 32) == 0 || xu >= (unsigned int)a.w) {
+        if (lane == 0) *a.score = -1;
+        return;
+    }
+    int x = (int)xu, i = 0;
+    if (lane == 0) a.xs[0] = x;
+    const int D = 2 * a.n - 1;
+    while (i < a.k) {
+        const bool ok = D <= 255    ? colwalk_trip<AT, 4, 8>(a, lane, x, i)
+                        : D <= 511  ? colwalk_trip<AT, 8, 0>(a, lane, x, i)
+                        : D <= 1023 ? colwalk_trip<AT, 16, 0>(a, lane, x, i)
+                                    : colwalk_trip<AT, 32, 0>(a, lane, x, i);
+        if (!ok) {
+            if (lane == 0) *a.score = -1;
+            return;
+        }
+    }
+    if (lane == 0) *a.score = (int)(m >> 32) - 1;
+}
+
 // ---- host side ---------------------------------------------------------------
 
 // Kernels of one step launch are chosen by this class; images of one class
@@ -1649,6 +1885,13 @@ const int32_t* last_table(const DpJobSpec& J) {
     return static_cast<const int32_t*>(band_table(J, J.g.k - 1));
 }
 
+// The column recurrence takes unbounded bends without a through-point pin,
+// k >= 2 and at least three displacements (its k rows of back-pointers fit
+// in the space of the k-2 planes, or one, of D rows each).
+bool colmax_apply(const DpJobSpec& J) {
+    return J.plan.kind == WindowKind::Full && J.pin.j < 0 && J.g.k >= 2 && J.g.D >= 3;
+}
+
 DpClass class_of(const DpJobSpec& j) {
     DpClass c;
     c.kind = (int)j.plan.kind;
@@ -1659,7 +1902,10 @@ DpClass class_of(const DpJobSpec& j) {
     c.narrow = j.tables.narrow > 0;
     c.steps = j.plan.steps;
     c.stripe = j.plan.stripe;
-    if (!fixed) c.kind = (int)WindowKind::Generic;  // one scanning kernel for every other kind
+    if (j.plan.kind == WindowKind::Full && colmax_apply(j))
+        c.kind = (int)WindowKind::Full;  // the column recurrence
+    else if (!fixed)
+        c.kind = (int)WindowKind::Generic;  // one scanning kernel for every other kind
     return c;
 }
 
@@ -2046,6 +2292,86 @@ hipError_t run_steps_grouped(const DpClass& c, int G, const std::vector<const Dp
     return launch_step<AT, CAP>(c, s, pk);
 }
 
+// Steps of the column recurrence for a pack of images: launch L makes band
+// Q-1-L of every image with more bands than that (Q: the most bands), so
+// every image's band 0 is in the final launch.  U_i goes to row 0 of value
+// plane i & 1, B_i to row i of the back-pointer space.  An image's top band
+// reads an int32 table and the others its narrow ones when it has them, so a
+// launch splits into a pack of each where both occur.
+template <typename AT, int CAP>
+hipError_t run_colmax(const DpClass& c, const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
+    int Q = 0;
+    for (const DpJobSpec* J : jobs) Q = std::max(Q, J->g.k);
+    TimedLaunch tl("dp_colmax", s, Q);
+    for (int L = 0; L < Q; ++L) {
+        const int i = Q - 1 - L;
+        for (int wide = 1; wide >= 0; --wide) {
+            ColPack<CAP> pk{};
+            long long total = 0;
+            int cnt = 0;
+            for (const DpJobSpec* J : jobs) {
+                const Geometry& g = J->g;
+                if (g.k <= i) continue;
+                const bool is_wide = i >= J->tables.narrow;
+                if (is_wide != (wide == 1)) continue;
+                const size_t plane = (size_t)g.D * g.pitch;
+                ColJob a{};
+                a.htab = band_table(*J, i);
+                a.uin = i == g.k - 1 ? nullptr : J->buf.vplanes + (size_t)((i + 1) & 1) * plane;
+                a.uout = i == 0 ? nullptr : J->buf.vplanes + (size_t)(i & 1) * plane;
+                a.bout = static_cast<AT*>(J->buf.a) + (size_t)i * g.pitch;
+                a.key = i == 0 ? J->buf.key : nullptr;
+                a.h_pitch = g.W;
+                a.n = g.n;
+                a.w = g.w;
+                a.item0 = (int)total;
+                total += (g.w + 63) / 64;
+                if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+                pk.job[cnt++] = a;
+            }
+            if (cnt == 0) continue;
+            pk.count = cnt;
+            const dim3 grid((unsigned)total), block(64 * kColWaves);
+            if (!wide && c.narrow)
+                hipLaunchKernelGGL((dp_colmax<AT, CAP, uint16_t>), grid, block, 0, s, pk);
+            else
+                hipLaunchKernelGGL((dp_colmax<AT, CAP, int32_t>), grid, block, 0, s, pk);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+template <typename AT, int CAP>
+hipError_t run_colmax_walks(const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
+    for (size_t q0 = 0; q0 < jobs.size(); q0 += CAP) {
+        ColWalkPack<CAP> pk{};
+        const int cnt = (int)std::min<size_t>(CAP, jobs.size() - q0);
+        for (int q = 0; q < cnt; ++q) {
+            const DpJobSpec& J = *jobs[q0 + q];
+            ColWalkJob& a = pk.job[q];
+            a.key = J.buf.key;
+            a.b_base = J.buf.a;
+            a.score = J.score;
+            a.xs = J.xs;
+            a.b_pitch = J.g.pitch;
+            a.n_keys = (J.g.w + 63) / 64;
+            a.n = J.g.n;
+            a.w = J.g.w;
+            a.k = J.g.k;
+        }
+        pk.count = cnt;
+        {
+            TimedLaunch tl("walk_colmax", s);
+            hipLaunchKernelGGL((walk_colmax<AT, CAP>), dim3(cnt), dim3(64), 0, s, pk);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename AT, int CAP>
 hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs,
                      const std::vector<std::pair<const DpJobSpec*, int>>& grouped, hipStream_t s) {
@@ -2128,6 +2454,7 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
         if (J->g.k >= 2) rest.push_back(J);
     std::vector<bool> done(rest.size(), false);
     std::vector<std::pair<const DpJobSpec*, int>> grouped;  // images whose steps went G per launch
+    std::vector<const DpJobSpec*> colmax, walked;  // the column recurrence, the others
     for (size_t q = 0; q < rest.size(); ++q) {
         if (done[q]) continue;
         const DpClass c = class_of(*rest[q]);
@@ -2140,6 +2467,12 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
         for (size_t q0 = 0; q0 < group.size(); q0 += CAP) {
             std::vector<const DpJobSpec*> pack(group.begin() + q0,
                                                group.begin() + std::min(group.size(), q0 + CAP));
+            if (c.kind == (int)WindowKind::Full) {
+                hipError_t e = run_colmax<AT, CAP>(c, pack, s);
+                if (e != hipSuccess) return e;
+                colmax.insert(colmax.end(), pack.begin(), pack.end());
+                continue;
+            }
             // G steps per launch when every image qualifies and one has a
             // group of G steps
             bool all2 = true, all3 = true;
@@ -2157,7 +2490,13 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
                 for (const DpJobSpec* J : pack) grouped.emplace_back(J, G);
         }
     }
-    return run_walks<AT, CAP>(jobs, grouped, s);
+    for (const DpJobSpec* J : jobs)
+        if (std::find(colmax.begin(), colmax.end(), J) == colmax.end()) walked.push_back(J);
+    if (!colmax.empty()) {
+        hipError_t e = run_colmax_walks<AT, CAP>(colmax, s);
+        if (e != hipSuccess) return e;
+    }
+    return run_walks<AT, CAP>(walked, grouped, s);
 }
 
 }  // namespace
