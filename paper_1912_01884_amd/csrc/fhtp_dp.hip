@@ -48,6 +48,7 @@
 // in the launches s = 0 .. k-2 of its pack (band i = k-2-s).  Two steps per
 // launch: images are aligned at their last step (run_steps_paired).
 #include <algorithm>
+#include <memory>
 #include <type_traits>
 #include <vector>
 
@@ -1245,6 +1246,200 @@ __global__ __launch_bounds__(64 * kWaves) void dp_step_generic(DpPack<CAP> pk) {
     finish(a, best, local);
 }
 
+// Step with per-displacement windows for bands of at most 255 displacements
+// and no pin (the angle form, mode-0 bounds above 16): a workgroup owns
+// kBlkCols successor columns x' and every displacement row, so each cell of
+// V_{i+1} is loaded once, into LDS, however many windows hold it.  The rows
+// are cut into blocks of kBlk; per column the workgroup keeps the maxima
+// from each block's start down to every row (prefix) and from every row to
+// its block's end (suffix), each with the smallest row reaching it, and a
+// sparse table of the block maxima over 1, 2, 4 and 8 consecutive blocks.
+// A window [lo, hi] inside one block is scanned directly (at most kBlk
+// cells); one that crosses blocks is the suffix at lo, at most two
+// overlapping runs of whole blocks, and the prefix at hi, taken in that
+// order with a later candidate winning only when larger, so ties keep the
+// smallest d' as everywhere else.
+constexpr int kBlkCols = 16;      // successor columns per workgroup
+constexpr int kBlk = 16;          // rows per block
+constexpr int kBlkRows = 256;     // rows held: D <= 255
+constexpr int kBlkLevels = 4;     // block runs of 1, 2, 4 and 8
+constexpr int kBlkThreads = 1024; // 16 waves: four per SIMD hide the LDS round trips
+constexpr int kBlkLanes = kBlkThreads / kBlkCols;  // row lanes
+constexpr int kBlkOut = kBlkRows / kBlkLanes;      // rows (cells) per thread
+
+template <typename AT, int CAP, typename TT>
+__global__ __launch_bounds__(kBlkThreads) void dp_step_blocks(DpPack<CAP> pk) {
+    constexpr int NB = kBlkRows / kBlk;
+    static_assert(NB * kBlkCols <= kBlkThreads, "one block scan per thread");
+    __shared__ int vt[kBlkRows][kBlkCols];       // V_{i+1}(X0 + c, row r), -1 where none
+    __shared__ int pre_v[kBlkRows][kBlkCols];    // max over [block start, r]
+    __shared__ int suf_v[kBlkRows][kBlkCols];    // max over [r, block end]
+    __shared__ unsigned char pre_i[kBlkRows][kBlkCols];  // its smallest row
+    __shared__ unsigned char suf_i[kBlkRows][kBlkCols];
+    __shared__ int run_v[kBlkLevels][NB][kBlkCols];  // max over blocks [b, b + 2^l)
+    __shared__ unsigned char run_i[kBlkLevels][NB][kBlkCols];
+    __shared__ unsigned char wlo[kBlkRows], whi[kBlkRows];  // window of each row, as rows
+
+    const int it = xcd_run_item((int)blockIdx.x, (int)gridDim.x);
+    const int jj = dp_find_job(pk, it);
+    const DpJob& a = pk.job[jj];
+    const int local = it - a.item0;  // the column tile
+    const int n = a.n, w = a.w, D = 2 * n - 1;
+    const int t = threadIdx.x;
+    const int c = t & (kBlkCols - 1);
+    const int rq = t / kBlkCols;  // first row of the thread's rows rq, rq + kBlkLanes, ...
+    const int xp = local * kBlkCols + c;
+
+    if (t < D) {
+        int lo, hi;
+        window_of(n, a.full, a.win, a.bound, t - (n - 1), lo, hi);
+        wlo[t] = (unsigned char)(lo + n - 1);
+        whi[t] = (unsigned char)(hi + n - 1);
+    }
+    // H_i(x' - d, d) of the thread's cells, then its rows of V_{i+1}
+    int hv[kBlkOut];
+#pragma unroll
+    for (int j = 0; j < kBlkOut; ++j) hv[j] = load_h<TT>(a, xp, rq + kBlkLanes * j - (n - 1));
+    const DRange mk = drange(n, xp, VMask{0, w, 0, w});
+#pragma unroll
+    for (int j = 0; j < kBlkOut; ++j) {
+        const int r = rq + kBlkLanes * j;
+        vt[r][c] = load_v(a.vin, a.vin_pitch, xp, r - (n - 1), n, mk);  // -1 past row D-1
+    }
+    __syncthreads();
+    if (rq < NB) {
+        // block rq of column c: prefix maxima ascending (ties keep the first),
+        // suffix maxima descending (ties move to the smaller row)
+        const int r0 = rq * kBlk;
+        int pv = kEmpty, pi = r0;
+#pragma unroll
+        for (int q = 0; q < kBlk; ++q) {
+            const int v = vt[r0 + q][c];
+            const bool take = v > pv;
+            pv = take ? v : pv;
+            pi = take ? r0 + q : pi;
+            pre_v[r0 + q][c] = pv;
+            pre_i[r0 + q][c] = (unsigned char)pi;
+        }
+        int sv = kEmpty, si = r0 + kBlk - 1;
+#pragma unroll
+        for (int q = kBlk - 1; q >= 0; --q) {
+            const int v = vt[r0 + q][c];
+            const bool take = v >= sv;
+            sv = take ? v : sv;
+            si = take ? r0 + q : si;
+            suf_v[r0 + q][c] = sv;
+            suf_i[r0 + q][c] = (unsigned char)si;
+        }
+        run_v[0][rq][c] = sv;
+        run_i[0][rq][c] = (unsigned char)si;
+    }
+    __syncthreads();
+    if (rq < NB) {
+        // runs of 2, 4, 8 blocks from block rq, ascending (ties keep the first)
+        int mv = run_v[0][rq][c], mi = run_i[0][rq][c];
+#pragma unroll
+        for (int l = 1; l < kBlkLevels; ++l) {
+#pragma unroll
+            for (int b = (1 << (l - 1)); b < (1 << l); ++b) {
+                const int bb = min(rq + b, NB - 1);
+                const int v = run_v[0][bb][c];
+                const bool take = rq + b < NB && v > mv;
+                mv = take ? v : mv;
+                mi = take ? run_i[0][bb][c] : mi;
+            }
+            run_v[l][rq][c] = mv;
+            run_i[l][rq][c] = (unsigned char)mi;
+        }
+    }
+    __syncthreads();
+
+    const bool last = a.key != nullptr;  // the image's last step: keys, no planes
+    const RowView ov = row_view(last ? a.vin : a.vout, a.v_pitch, 4, 0, D, D);
+    const RowView av = row_view(last ? a.vin : a.aout, a.a_pitch, sizeof(AT), 0, D, D);
+    const bool col = xp < w;
+    Best best;
+#pragma unroll
+    for (int j = 0; j < kBlkOut; ++j) {
+        const int r = rq + kBlkLanes * j;
+        if (r >= D) break;
+        const int lo = wlo[r], hi = whi[r];
+        const int bl = lo / kBlk, bh = hi / kBlk;
+        int m, ia;
+        if (bl == bh) {
+            m = kEmpty;
+            ia = lo;
+            for (int q = lo; q <= hi; ++q) {
+                const int v = vt[q][c];
+                const bool take = v > m;
+                m = take ? v : m;
+                ia = take ? q : ia;
+            }
+        } else {
+            m = suf_v[lo][c];
+            ia = suf_i[lo][c];
+            const int cnt = bh - bl - 1;  // whole blocks between
+            if (cnt > 0) {
+                const int l = 31 - __builtin_clz((unsigned)cnt);
+                const int v1 = run_v[l][bl + 1][c], v2 = run_v[l][bh - (1 << l)][c];
+                const bool t1 = v1 > m;
+                m = t1 ? v1 : m;
+                ia = t1 ? run_i[l][bl + 1][c] : ia;
+                const bool t2 = v2 > m;
+                m = t2 ? v2 : m;
+                ia = t2 ? run_i[l][bh - (1 << l)][c] : ia;
+            }
+            const int vp = pre_v[hi][c];
+            const bool tp = vp > m;
+            m = tp ? vp : m;
+            ia = tp ? pre_i[hi][c] : ia;
+        }
+        if (!col) continue;
+        if (last) {
+            const int x = xp - (r - (n - 1));
+            if ((unsigned)x < (unsigned)w) take_best(best, pack_key(m >= 0 ? hv[j] + m : -1, x, r, D), ia);
+            continue;
+        }
+        const unsigned int aoff = (unsigned int)r * a.a_pitch * sizeof(AT) + (unsigned int)xp * sizeof(AT);
+        if constexpr (sizeof(AT) == 1)
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)ia, av.rs, (int)aoff, 0, kStoreScope);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)ia, av.rs, (int)aoff, 0, kStoreScope);
+        const int x = xp - (r - (n - 1));
+        if ((unsigned)x < (unsigned)w) {
+            const int val = m >= 0 ? hv[j] + m : -1;
+            __builtin_amdgcn_raw_buffer_store_b32(
+                val, ov.rs, (int)((unsigned int)r * a.v_pitch * 4u + (unsigned int)x * 4u), 0,
+                kStoreScope);
+        }
+    }
+    if (last) {
+        // the workgroup's best key and that cell's successor, slot = column tile
+        constexpr int W = kBlkThreads / 64;
+        __shared__ unsigned long long part[W];
+        __shared__ int part_s[W];
+        const int lane = t & 63, wave = t >> 6;
+        best = wave_best(best);
+        if (lane == 0) {
+            part[wave] = best.key;
+            part_s[wave] = best.succ;
+        }
+        __syncthreads();
+        if (t == 0) {
+            unsigned long long mk2 = part[0];
+            int ms = part_s[0];
+#pragma unroll
+            for (int q = 1; q < W; ++q) {
+                const bool tk = part[q] > mk2;
+                mk2 = tk ? part[q] : mk2;
+                ms = tk ? part_s[q] : ms;
+            }
+            a.key[local] = mk2;
+            a.succ[local] = ms;
+        }
+    }
+}
+
 // k = 1: the answer is the best masked cell of H_0 (htab), pinned as vin.
 template <int CAP>
 __global__ __launch_bounds__(64 * kWaves) void argmax_table(DpPack<CAP> pk) {
@@ -1601,22 +1796,32 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
 }
 
 // Mode-1 windows: lo(d) and hi(d) bracket every d' with n*|d'-d| <= t*(n*n + d*d').
-__global__ void angle_windows(int n, double t, int32_t* __restrict__ win) {
+// One wave per d: the lanes test 64 candidates d' at a time and the first
+// and last admissible ones come from the wave's ballot.  Both sides of the
+// test are exact products of integers below 2^22 except the one rounding of
+// t times the integer, so the result does not depend on how the compiler
+// groups the arithmetic.
+__global__ __launch_bounds__(64) void angle_windows(int n, double t, int32_t* __restrict__ win) {
     const int D = 2 * n - 1;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= D) return;
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x;
     const int d = r - (n - 1);
     int lo = n, hi = -n;
-    for (int dp = -(n - 1); dp <= n - 1; ++dp) {
+    for (int q0 = 0; q0 < D; q0 += 64) {
+        const int q = q0 + lane;
+        const int dp = q - (n - 1);
         const double lhs = (double)n * (double)abs(dp - d);
         const double rhs = t * ((double)n * (double)n + (double)d * (double)dp);
-        if (lhs <= rhs) {
-            if (lo == n) lo = dp;
-            hi = dp;
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(q < D && lhs <= rhs);
+        if (m) {
+            if (lo == n) lo = q0 + (int)__builtin_ctzll(m) - (n - 1);
+            hi = q0 + 63 - (int)__builtin_clzll(m) - (n - 1);
         }
     }
-    win[r] = lo;
-    win[D + r] = hi;
+    if (lane == 0) {
+        win[r] = lo;
+        win[D + r] = hi;
+    }
 }
 
 // ---- unbounded bend: the column-maximum recurrence ---------------------------
@@ -1976,16 +2181,47 @@ DpJob base_job(const DpJobSpec& J) {
     return a;
 }
 
+// The block kernel takes scanned windows (the angle form, bounds above the
+// fixed-window kernels') of bands with at most 255 displacements, without a
+// through-point pin.
+bool blocks_apply(const DpJobSpec& J) {
+    return (J.plan.kind == WindowKind::Angle || J.plan.kind == WindowKind::Generic) &&
+           J.pin.j < 0 && J.g.D <= kBlkRows - 1;
+}
+
 // Steps of a pack of images of one class (each with k >= 2).
 template <typename AT, int CAP>
 hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs, hipStream_t s) {
     int max_steps = 0;
     for (const DpJobSpec* J : jobs) max_steps = std::max(max_steps, J->g.k - 1);
-    TimedLaunch tl(step_family(c), s, max_steps);
+    // Steps that take the block kernel and the others, each run of launches
+    // of one kernel in one timing bracket.
+    auto blocks_at = [&](const DpJobSpec& J, int) { return blocks_apply(J); };
+    std::vector<const char*> seq;  // kernel family of every launch, in order
     for (int st = 0; st < max_steps; ++st) {
-        DpPack<CAP> pk{};
-        long long total = 0;
-        int cnt = 0;
+        bool b = false, o = false;
+        for (const DpJobSpec* J : jobs) {
+            if (J->g.k - 1 <= st) continue;
+            (blocks_at(*J, st) ? b : o) = true;
+        }
+        if (b) seq.push_back("dp_step_blocks");
+        if (o) seq.push_back(step_family(c));
+    }
+    std::unique_ptr<TimedLaunch> tl;
+    size_t q = 0;
+    auto bracket = [&]() {  // before launch q: a bracket per run of one family
+        if (q == 0 || seq[q] != seq[q - 1]) {
+            tl.reset();
+            size_t e = q;
+            while (e < seq.size() && seq[e] == seq[q]) ++e;
+            tl.reset(new TimedLaunch(seq[q], s, (int)(e - q)));
+        }
+        ++q;
+    };
+    for (int st = 0; st < max_steps; ++st) {
+        DpPack<CAP> pk{}, pb{};
+        long long total = 0, tb = 0;
+        int cnt = 0, cb = 0;
         for (const DpJobSpec* J : jobs) {
             const Geometry& g = J->g;
             if (g.k - 1 <= st) continue;
@@ -2005,16 +2241,41 @@ hipError_t run_steps(const DpClass& c, const std::vector<const DpJobSpec*>& jobs
             a.succ = last ? J->buf.succ : nullptr;
             if (st == 0) first_step_pin(*J, a.vin_pin, a.vin_pin_x);
             a.out_pin_x = J->pin.j == i ? J->pin.x : -1;
+            if (blocks_at(*J, st)) {
+                a.items_x = (g.w + kBlkCols - 1) / kBlkCols;
+                a.items_y = 1;
+                a.item0 = (int)tb;
+                tb += a.items_x;
+                if (tb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+                pb.job[cb++] = a;
+                continue;
+            }
             a.items_y = items_y_of(g, c.dc);
             a.item0 = (int)total;
             total += (long long)a.items_x * a.items_y;
             if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
             pk.job[cnt++] = a;
         }
-        pk.count = cnt;
-        pk.total = (int)total;
-        hipError_t e = launch_step<AT, CAP>(c, s, pk);
-        if (e != hipSuccess) return e;
+        if (cb > 0) {
+            pb.count = cb;
+            pb.total = (int)tb;
+            bracket();
+            if (c.narrow)
+                hipLaunchKernelGGL((dp_step_blocks<AT, CAP, uint16_t>), dim3((unsigned)tb),
+                                   dim3(kBlkThreads), 0, s, pb);
+            else
+                hipLaunchKernelGGL((dp_step_blocks<AT, CAP, int32_t>), dim3((unsigned)tb),
+                                   dim3(kBlkThreads), 0, s, pb);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (cnt > 0) {
+            pk.count = cnt;
+            pk.total = (int)total;
+            bracket();
+            hipError_t e = launch_step<AT, CAP>(c, s, pk);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -2385,8 +2646,9 @@ hipError_t run_walks(const std::vector<const DpJobSpec*>& jobs,
             WalkJob& a = pk.job[q];
             a.key = J.buf.key;
             a.succ = J.buf.succ;
-            a.n_keys = g.k == 1 ? (int)(((g.w + 63) / 64) * items_y_of(g, kDCGeneric))
-                                : (int)(((g.w + 63) / 64) * items_y_of(g, c.dc));
+            a.n_keys = g.k == 1        ? (int)(((g.w + 63) / 64) * items_y_of(g, kDCGeneric))
+                       : blocks_apply(J) ? (g.w + kBlkCols - 1) / kBlkCols  // one per column tile
+                                         : (int)(((g.w + 63) / 64) * items_y_of(g, c.dc));
             a.a_base = J.buf.a;
             a.a_plane = (size_t)g.D * g.pitch;
             a.a_pitch = g.pitch;
@@ -2504,8 +2766,12 @@ hipError_t launch_dp_jobs_t(const std::vector<const DpJobSpec*>& jobs, hipStream
 size_t dp_plane_bytes(const Geometry& g) { return (size_t)g.D * g.pitch * sizeof(int32_t); }
 
 size_t dp_key_count(const Geometry& g) {
-    // workgroups of the last step at 8 displacements per thread (the largest grid)
-    return (size_t)((g.w + 63) / 64) * items_y_of(g, 8);
+    // workgroups of the last step: at 8 displacements per thread (the
+    // largest grid of the 64-column kernels), or one per column tile of the
+    // block kernel
+    const size_t k64 = (size_t)((g.w + 63) / 64) * items_y_of(g, 8);
+    const size_t k16 = (size_t)((g.w + kBlkCols - 1) / kBlkCols);
+    return k64 > k16 ? k64 : k16;
 }
 
 size_t dp_backptr_bytes(const Geometry& g, bool a16) {
@@ -2525,7 +2791,7 @@ hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t s) {
             return hipErrorInvalidValue;
         if (J.plan.kind == WindowKind::Angle) {
             TimedLaunch tl("angle_windows", s);
-            hipLaunchKernelGGL(angle_windows, dim3((J.g.D + 255) / 256), dim3(256), 0, s, J.g.n,
+            hipLaunchKernelGGL(angle_windows, dim3(J.g.D), dim3(64), 0, s, J.g.n,
                                J.plan.tan_gamma, J.buf.win);
         }
         (J.plan.a16 ? a16 : a8).push_back(&J);
