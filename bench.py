@@ -34,16 +34,16 @@ HBM_PEAK_GBPS = 8000.0
 TRAFFIC = {
     "fht_reg_kernel": {"source": "paper_1912_01884_amd/csrc/fhtp_fht.hip",
                       "source_sha256": "e3cdf11d01e858cd2cdd5454bc92dd819b4aeca9c3ccca1ab77b38906fe3cc4b",
-                      "fetch_bytes": 41997953, "write_bytes": 151428160},
+                      "fetch_bytes": 42428983, "write_bytes": 151249952},
     "dp_pair_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
-                     "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
-                     "fetch_bytes": 13989872, "write_bytes": 6653440},
+                     "source_sha256": "4149219b3c9bf6dc7417d146a744ebf62f492c8b091e440efef3a66ad3b0b50e",
+                     "fetch_bytes": 14002144, "write_bytes": 6653440},
     "dp_step_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
-                     "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
-                     "fetch_bytes": 8698177, "write_bytes": 6144},
+                     "source_sha256": "4149219b3c9bf6dc7417d146a744ebf62f492c8b091e440efef3a66ad3b0b50e",
+                     "fetch_bytes": 8698173, "write_bytes": 6144},
     "walk": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
-            "source_sha256": "2c3e39e2e9e9079428a43a2431c7787ef11e8f05f3ff22d3b8c90c0cf3121d46",
-            "fetch_bytes": 135535, "write_bytes": 192},
+            "source_sha256": "4149219b3c9bf6dc7417d146a744ebf62f492c8b091e440efef3a66ad3b0b50e",
+            "fetch_bytes": 138607, "write_bytes": 192},
 }
 
 
@@ -582,6 +582,9 @@ def main():
                     help="skip the 64x64 and 1024x1024 workloads")
     ap.add_argument("--no-tune", action="store_true",
                     help="run with the library's default launch shapes (no autotuning)")
+    ap.add_argument("--dp-steps", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="force this many DP steps per launch for fixed windows instead of "
+                         "tuning (for profiling one kernel family; 0: tune)")
     ap.add_argument("--plan-out", default=None,
                     help="save the mixed workload's tuned rules to this JSON file")
     ap.add_argument("--probe", action="store_true",
@@ -609,6 +612,9 @@ def main():
     import synth
     from paper_1912_01884_amd import fhtp
 
+    from paper_1912_01884_amd import autotune
+    if args.dp_steps:
+        fhtp.tune_set([autotune.rule(window=0, dc=8, steps=args.dp_steps)])
     if args.probe:
         probe(torch.device("cuda:0"))
         return
@@ -630,9 +636,8 @@ def main():
 
     # Launch shapes for this workload, picked by the autotuner before the
     # timed region (results are the same under every candidate).
-    from paper_1912_01884_amd import autotune
-    tuning = None
-    if not args.no_tune:
+    tuning = {"forced_dp_steps": args.dp_steps} if args.dp_steps else None
+    if not args.no_tune and not args.dp_steps:
         tuning = autotune.tune([img], [k], bends=[B], reps=max(5, args.steps // 2),
                                stream=stream).as_dict()
 
