@@ -576,6 +576,8 @@ def main():
                          "(0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per arrival rate in the serving run (0 skips it)")
+    ap.add_argument("--serve-streams", type=int, default=4,
+                    help="streams of the continuous-batching server (groups in flight at once)")
     ap.add_argument("--serve-rates", default="200,1000,5000,inf",
                     help="Poisson arrival rates (requests/s) of the serving run; inf = all at once")
     ap.add_argument("--no-other-configs", action="store_true",
@@ -799,7 +801,7 @@ def main():
                                           tune=not args.no_tune, plan_out=args.plan_out)
     if args.serve_requests > 0:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
-        line["serving"] = serving(dev, rates, args.serve_requests)
+        line["serving"] = serving(dev, rates, args.serve_requests, streams=args.serve_streams)
         k1000 = line["serving"].get("1000_per_s")
         if k1000:
             line["p99_ms"] = k1000["server"]["p99_ms"]

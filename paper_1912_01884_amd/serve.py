@@ -31,6 +31,7 @@ from __future__ import annotations
 import bisect
 import collections
 import ctypes as C
+import gc
 import math
 import time
 from dataclasses import dataclass, field
@@ -282,6 +283,10 @@ class FhtpBackend:
         self.base = self.arena.data_ptr()
         self._bytes: dict = {}  # workspace bytes per request shape
         self.streams = [torch.cuda.Stream(self.device) for _ in range(streams)]
+        # one completion event per stream: a stream carries one group at a time
+        # (the server frees it only after its group's event has fired), so the
+        # event is re-recorded for each group instead of created anew
+        self.events = [torch.cuda.Event() for _ in range(streams)]
         # the arena's allocation is ordered before any group on any stream
         torch.cuda.synchronize(self.device)
 
@@ -309,7 +314,7 @@ class FhtpBackend:
         rc = self.L.fhtp_detect_batch(arr, len(jobs), C.c_void_p(self.base + offset), nbytes,
                                       C.c_void_p(s.cuda_stream))
         self.fhtp._check(rc, "detect_batch")
-        ev = self.torch.cuda.Event()
+        ev = self.events[stream]
         ev.record(s)
         return ev
 
@@ -332,6 +337,7 @@ class PlainServer:
         self.ws = torch.empty(max(align_up(max_request_bytes), ALIGN), dtype=torch.uint8,
                               device=self.device)
         self.stream = torch.cuda.Stream(self.device)
+        self.event = torch.cuda.Event()
         self._bytes: dict = {}  # workspace bytes per request shape
         self.clock = clock
         self.waiting: Deque[Request] = collections.deque()
@@ -369,9 +375,8 @@ class PlainServer:
                 C.c_void_p(r.score.data_ptr()), C.c_void_p(r.xs.data_ptr()),
                 C.c_void_p(self.stream.cuda_stream))
             F._check(rc, "detect_polyline")
-            ev = self.torch.cuda.Event()
-            ev.record(self.stream)
-            self.current = (r, ev)
+            self.event.record(self.stream)  # one request in flight at a time
+            self.current = (r, self.event)
         return out
 
     def drain(self, timeout: float = 60.0) -> List[Request]:
@@ -400,8 +405,20 @@ def run_open_loop(server, requests: List[Request], arrivals: List[float],
     """Submit each request at its arrival time (relative to now) and poll until all finish.
 
     Latency is completion (observed by the host) minus the scheduled arrival,
-    so any lag of the loop itself counts against the server.
+    so any lag of the loop itself counts against the server.  Python's cyclic
+    garbage collector is paused for the run (its pauses would land in the
+    tail of whichever request was in flight); it runs again afterwards.
     """
+    enabled = gc.isenabled()
+    gc.disable()
+    try:
+        return _open_loop(server, requests, arrivals, timeout)
+    finally:
+        if enabled:
+            gc.enable()
+
+
+def _open_loop(server, requests: List[Request], arrivals: List[float], timeout: float) -> dict:
     clock = server.clock
     t0 = clock()
     order = sorted(range(len(requests)), key=lambda i: arrivals[i])
