@@ -304,7 +304,13 @@ int fhtp_plan_destroy(fhtp_plan plan);
  *   stripe:   column tiles per stripe of the multi-step kernels' workgroup
  *             order, 1..64 (0: 16);
  *   fht_grid: 0: the FHT's resident grid loops over the work items; 1: one
- *             workgroup per work item.
+ *             workgroup per work item;
+ *   small:    0: a detection whose bands are at most 32 rows high and whose
+ *             image, tables, value planes and back-pointers fit in 64 KB (and
+ *             that has no through-point pin) runs as one workgroup doing the
+ *             whole detection in LDS, in a batch always and alone while its
+ *             work stays near that of a 64 x 64 image with k = 4; 1: never
+ *             (the general kernels).
  * fhtp_tune_set replaces the process-wide rule list (count 0 clears it); at
  *   most 1024 rules, each validated (FHTP_ERR_OPTION, nothing changed, if one
  *   is out of range).  Requests are matched against the rules, first match
@@ -324,6 +330,7 @@ typedef struct {
     int32_t steps;
     int32_t stripe;
     int32_t fht_grid;
+    int32_t small;
 } fhtp_tune_rule;
 
 int fhtp_tune_set(const fhtp_tune_rule* rules, int count);

@@ -42,11 +42,11 @@ DP_CANDIDATES = ([dict(dc=8, steps=g, stripe=s) for g in (3, 2) for s in (4, 8, 
 FHT_CANDIDATES = (0, 1)
 
 
-def rule(dtype=-1, log2n=-1, window=-1, dc=0, steps=0, stripe=0, fht_grid=0,
+def rule(dtype=-1, log2n=-1, window=-1, dc=0, steps=0, stripe=0, fht_grid=0, small=0,
          w_min=W_ANY[0], w_max=W_ANY[1]) -> dict:
     return dict(dtype=int(dtype), log2n=int(log2n), w_min=int(w_min), w_max=int(w_max),
                 window=int(window), dc=int(dc), steps=int(steps), stripe=int(stripe),
-                fht_grid=int(fht_grid))
+                fht_grid=int(fht_grid), small=int(small))
 
 
 def device_key() -> dict:
@@ -204,7 +204,7 @@ def load(path: str, install_rules: bool = True) -> Optional[List[dict]]:
     if doc.get("key") != device_key():
         return None
     rules = [rule(**{k: r[k] for k in ("dtype", "log2n", "window", "dc", "steps", "stripe",
-                                       "fht_grid", "w_min", "w_max")})
+                                       "fht_grid", "small", "w_min", "w_max") if k in r})
              for r in doc["rules"]]
     if install_rules:
         install(rules)

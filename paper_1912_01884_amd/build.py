@@ -23,7 +23,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfhtp.so")
 ARCH = "gfx950"
 
-SOURCES = ["fhtp_api.cpp", "fhtp_timing.cpp", "fhtp_fht.hip", "fhtp_dp.hip", "fhtp_prep.hip"]
+SOURCES = ["fhtp_api.cpp", "fhtp_timing.cpp", "fhtp_fht.hip", "fhtp_dp.hip", "fhtp_prep.hip",
+           "fhtp_small.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

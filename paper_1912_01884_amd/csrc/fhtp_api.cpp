@@ -4,6 +4,7 @@
 // outputs untouched.
 #include "fhtp.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -79,7 +80,8 @@ bool rule_valid(const fhtp_tune_rule& r) {
     return r.dtype >= -1 && r.dtype <= 1 && r.log2n >= -1 && r.log2n <= 10 && r.w_min >= 0 &&
            r.w_min <= r.w_max && r.window >= -1 && r.window <= 1 &&
            (r.dc == 0 || r.dc == 8 || r.dc == 16) && (r.steps >= 0 && r.steps <= 3) &&
-           r.stripe >= 0 && r.stripe <= 64 && (r.fht_grid == 0 || r.fht_grid == 1);
+           r.stripe >= 0 && r.stripe <= 64 && (r.fht_grid == 0 || r.fht_grid == 1) &&
+           (r.small == 0 || r.small == 1);
 }
 
 // Knobs for a planned request: dtype -1 when the pixel type is not part of
@@ -96,6 +98,7 @@ void apply_tuning(const fhtp::Geometry& g, int dtype, fhtp::DpPlan* pl) {
         if (r.steps) pl->steps = r.steps;
         pl->stripe = r.stripe ? r.stripe : 16;
         pl->fht_grid = r.fht_grid;
+        pl->small = r.small == 0;
         return;
     }
 }
@@ -107,6 +110,7 @@ int plan_window(const fhtp::Geometry& g, fhtp_bend b, fhtp::DpPlan* pl) {
     pl->steps = 2;
     pl->stripe = 16;
     pl->fht_grid = 0;
+    pl->small = true;
     pl->bound = 0;
     pl->tan_gamma = 0.0;
     if (b.mode == 0) {
@@ -350,6 +354,10 @@ int fhtp_detect_polyline(const void* img, fhtp_dtype dtype, int h, int w, int k,
     const fhtp::TableSet tables = table_set(base, L);
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
+    if (fhtp::small_apply(g, (int)dtype, pl, fhtp::Pin{}, true)) {
+        const fhtp::SmallJobSpec j{img, (int)dtype, g, pl, score, xs};
+        return hip_status(fhtp::launch_small_jobs(&j, 1, s), "detect_polyline/small");
+    }
     rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s, pl.fht_grid),
                     "detect_polyline/fht");
     if (rc != FHTP_OK) return rc;
@@ -469,6 +477,10 @@ int fhtp_detect_polyline_noalloc(const void* img, fhtp_dtype dtype, int h, int w
     const fhtp::TableSet tables = table_set(base, L);
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
+    if (fhtp::small_apply(g, (int)dtype, pl, fhtp::Pin{}, true)) {
+        const fhtp::SmallJobSpec j{img, (int)dtype, g, pl, score, xs};
+        return hip_status(fhtp::launch_small_jobs(&j, 1, s), "detect_polyline_noalloc/small");
+    }
     rc = hip_status(fhtp::launch_fht(img, (int)dtype, g, tables, base + L.scratch, s, pl.fht_grid),
                     "detect_polyline_noalloc/fht");
     if (rc != FHTP_OK) return rc;
@@ -506,6 +518,10 @@ int fhtp_detect_polyline_ex(const void* img, fhtp_dtype dtype, int h, int w, int
         if (rc != FHTP_OK) return rc;
         det = base;
         base += e.prep_bytes;
+    }
+    if (fhtp::small_apply(e.g, (int)dtype, e.pl, e.pin, true)) {
+        const fhtp::SmallJobSpec j{det, (int)dtype, e.g, e.pl, score, xs};
+        return hip_status(fhtp::launch_small_jobs(&j, 1, s), "detect_polyline_ex/small");
     }
     const fhtp::TableSet tables = table_set(base, e.L);
     rc = hip_status(fhtp::launch_fht(det, (int)dtype, e.g, tables, base + e.L.scratch, s,
@@ -680,15 +696,30 @@ int detect_batch_on(const fhtp_job* jobs, int count, void* ws, size_t ws_bytes, 
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
+    // small images: one fused workgroup each, in their own launches
+    std::vector<fhtp::SmallJobSpec> small;
     std::vector<int> tall, rest;
-    for (int q = 0; q < count; ++q) (dj[q].plan.a16 ? tall : rest).push_back(q);
+    for (int q = 0; q < count; ++q) {
+        if (fhtp::small_apply(dj[q].g, fj[q].dtype, dj[q].plan, fhtp::Pin{}, false))
+            small.push_back(fhtp::SmallJobSpec{fj[q].img, fj[q].dtype, dj[q].g, dj[q].plan,
+                                               dj[q].score, dj[q].xs});
+        else
+            (dj[q].plan.a16 ? tall : rest).push_back(q);
+    }
+    if (!small.empty()) {
+        rc = hip_status(fhtp::launch_small_jobs(small.data(), (int)small.size(), s),
+                        "detect_batch/small");
+        if (rc != FHTP_OK) return rc;
+    }
+    if (tall.empty() && rest.empty()) return FHTP_OK;
     Aux* ax = nullptr;
     if (!tall.empty() && !rest.empty()) ax = ax_given ? ax_given : aux_for_caller(s);
     if (ax && !ax->ok) ax = nullptr;
-    if (!ax) {
-        rc = hip_status(fhtp::launch_fht_jobs(fj.data(), count, s), "detect_batch/fht");
-        if (rc != FHTP_OK) return rc;
-        return hip_status(fhtp::launch_dp_jobs(dj.data(), count, s), "detect_batch/dp");
+    if (!ax) {  // every remaining image on the caller's stream
+        std::vector<int> all(tall);
+        all.insert(all.end(), rest.begin(), rest.end());
+        std::sort(all.begin(), all.end());
+        return run_subset(fj, dj, all, s);
     }
     std::lock_guard<std::mutex> lock(ax->mu);
     rc = hip_status(hipEventRecord(ax->fork, s), "detect_batch/fork");

@@ -92,6 +92,7 @@ struct DpPlan {
     int steps = 2;      // most DP steps per launch (1..3) where the window allows them
     int stripe = 16;    // column tiles per stripe of the multi-step kernels' item order
     int fht_grid = 0;   // the detection's FHT: 0 resident grid, 1 one workgroup per item
+    bool small = true;  // small images may take the one-workgroup path
 };
 
 struct DpBuffers {
@@ -127,6 +128,22 @@ struct DpJobSpec {
 };
 // Several images; images of one window class share every step launch.
 hipError_t launch_dp_jobs(const DpJobSpec* jobs, int count, hipStream_t stream);
+
+// ---- small images: the whole detection in one workgroup ----------------------
+struct SmallJobSpec {
+    const void* img;
+    int dtype;  // 0 = uint8, 1 = uint16
+    Geometry g;
+    DpPlan plan;
+    int32_t* score;
+    int32_t* xs;
+};
+// Whether a detection runs as one workgroup with everything in LDS (bands of
+// at most 32 rows, the image, tables, value planes and back-pointers within
+// 64 KB, no pin; alone, i.e. not in a batch, also little enough work).
+bool small_apply(const Geometry& g, int dtype, const DpPlan& pl, Pin pin, bool alone);
+// Those detections, one workgroup per image, in packs.
+hipError_t launch_small_jobs(const SmallJobSpec* jobs, int count, hipStream_t stream);
 
 // ---- optional input steps ---------------------------------------------------
 // Detection image from the input: transposed when `transpose` (mostly

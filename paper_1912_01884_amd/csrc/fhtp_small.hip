@@ -1,0 +1,375 @@
+// Whole detections of small images in one launch: the band line sums
+// (Section 2.1, eq. (1)), every DP step with its bend window (Sections
+// 2.2-2.3, eqs. (3)-(4) and (6)-(7)), the global choice (main problem, steps
+// 2-3) and the backtrace (eq. (5)), one workgroup per image with everything
+// in LDS.
+//
+// For an image whose bands are at most 32 rows high and whose tables, value
+// planes and back-pointers fit in 64 KB, the general path's launches (the
+// FHT, one per one or two DP steps, the walk) are each a few microseconds of
+// launch latency around very little work.  Here a workgroup loads the image
+// into LDS once, then runs band by band from the bottom: the line sums H_i(x, d)
+// for the cells the DP uses (x in [0, w), x + d in [0, w)) summed directly
+// along the dyadic line, then the DP step on the previous band's values in
+// LDS.  Line sums are exact integers, so summing a line directly gives the
+// same value as the stage recursion.  The dyadic offsets come from the
+// recursive definition: the upper half of the line with shift s over n rows
+// is the line with shift floor(s/2) over n/2 rows, the lower half the same
+// line moved right by ceil(s/2); left-leaning lines mirror it.  Window maxima
+// are scanned in ascending row order (ties to the smallest d'), the keys pick
+// the largest value with the smallest (x, d), and the walk follows the
+// back-pointers held in LDS: the same result as the general path, bit for
+// bit.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "fhtp_internal.h"
+
+namespace fhtp {
+namespace {
+
+constexpr int kSmallThreads = 1024;  // 16 waves on the workgroup's CU
+constexpr int kSmallMaxN = 32;
+constexpr size_t kSmallLds = 64 * 1024;
+constexpr int kSmallPack = 256;  // images per launch
+
+struct SmallJob {
+    const void* img;
+    int32_t* score;
+    int32_t* xs;
+    int h, w, k, n;
+    int kind;      // WindowKind
+    int bound;     // mode-0 bound
+    double tan_g;  // mode 1
+};
+
+template <int CAP>
+struct SmallPack {
+    SmallJob job[CAP];
+    int count;
+};
+
+__host__ __device__ inline size_t align4(size_t b) { return (b + 3) & ~size_t(3); }
+
+// LDS bytes of one image: its pixels, the dyadic offsets, a band's line sums
+// and two value planes, the back-pointers of every step, windows.
+size_t small_lds_bytes(int n, int w, int k, int bpp) {
+    const size_t D = 2 * (size_t)n - 1;
+    return (kSmallThreads / 64) * 8 + align4((size_t)n * k * w * bpp) + align4((size_t)n * n) +
+           3 * D * w * 4 + align4((size_t)(k > 1 ? k - 1 : 0) * D * w) + 2 * D * 4;
+}
+
+__device__ __forceinline__ unsigned long long small_key(int val, int x, int r, int D) {
+    const unsigned int lin = (unsigned int)x * (unsigned int)D + (unsigned int)r;
+    return ((unsigned long long)(unsigned int)(val + 1) << 32) |
+           (unsigned long long)(0xffffffffu - lin);
+}
+
+// N: the band height (a compile-time constant, so that a line's N reads are
+// unrolled and in flight together).
+template <typename PixT, int N, int CAP>
+__global__ __launch_bounds__(kSmallThreads) void detect_small(SmallPack<CAP> pk) {
+    extern __shared__ unsigned long long small_lds[];
+    const SmallJob& a = pk.job[blockIdx.x];
+    constexpr int n = N, D = 2 * N - 1;
+    const int w = a.w, k = a.k;
+    const int t = threadIdx.x;
+    const int cells = D * w;
+    constexpr int kRowLanes = kSmallThreads / 64;
+    const int cx = t & 63, ry = t >> 6;  // column lane, row lane
+    unsigned long long* part = small_lds;  // one key per wave
+    char* base = reinterpret_cast<char*>(small_lds + kSmallThreads / 64);
+    PixT* img = reinterpret_cast<PixT*>(base);  // the whole image
+    base += align4((size_t)n * k * w * sizeof(PixT));
+    unsigned char* off = reinterpret_cast<unsigned char*>(base);  // off[s * n + y]
+    base += align4((size_t)n * n);
+    int* H = reinterpret_cast<int*>(base);
+    int* Vp = H + cells;      // values of the band below (V_{i+1})
+    int* Vc = Vp + cells;     // values of this band (V_i)
+    unsigned char* A = reinterpret_cast<unsigned char*>(Vc + cells);  // A[i][r][x']
+    base = reinterpret_cast<char*>(A) + align4((size_t)(k > 1 ? k - 1 : 0) * cells);
+    int* wlo = reinterpret_cast<int*>(base);
+    int* whi = wlo + D;
+
+    // the image, once: 16-byte loads when the source is aligned, four in
+    // flight per thread, then the bytes left over
+    {
+        const int bytes = n * k * w * (int)sizeof(PixT);
+        const char* src = static_cast<const char*>(a.img);
+        char* dst = reinterpret_cast<char*>(img);
+        int done = 0;
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            const int n16 = bytes / 16;
+            const uint4* s16 = reinterpret_cast<const uint4*>(src);
+            uint4* d16 = reinterpret_cast<uint4*>(dst);
+            for (int q0 = t; q0 < n16; q0 += 4 * kSmallThreads) {
+                uint4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u * kSmallThreads;
+                    v[u] = s16[q < n16 ? q : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u * kSmallThreads;
+                    if (q < n16) d16[q] = v[u];
+                }
+            }
+            done = n16 * 16;
+        }
+        for (int q0 = done + t; q0 < bytes; q0 += 4 * kSmallThreads) {
+            char v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * kSmallThreads;
+                v[u] = src[q < bytes ? q : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * kSmallThreads;
+                if (q < bytes) dst[q] = v[u];
+            }
+        }
+    }
+    // dyadic offsets D_s(y), s, y in [0, n): a row's bits from the top level down
+    constexpr int p = N >= 32 ? 5 : N >= 16 ? 4 : N >= 8 ? 3 : N >= 4 ? 2 : N >= 2 ? 1 : 0;
+    for (int q = t; q < n * n; q += kSmallThreads) {
+        int s = q / n, y = q - (q / n) * n, o = 0;
+        for (int l = p; l >= 1; --l) {
+            const int half = 1 << (l - 1);
+            if (y >= half) {
+                o += (s + 1) >> 1;
+                y -= half;
+            }
+            s >>= 1;
+        }
+        off[q] = (unsigned char)o;
+    }
+    // windows [lo, hi] of every displacement, as rows
+    for (int r = t; r < D; r += kSmallThreads) {
+        const int d = r - (n - 1);
+        int lo, hi;
+        if (a.kind == (int)WindowKind::Angle) {
+            lo = D;
+            hi = -1;
+            for (int rp = 0; rp < D; ++rp) {
+                const int dp = rp - (n - 1);
+                const double lhs = (double)n * (double)abs(dp - d);
+                const double rhs = a.tan_g * ((double)n * (double)n + (double)d * (double)dp);
+                if (lhs <= rhs) {
+                    lo = min(lo, rp);
+                    hi = max(hi, rp);
+                }
+            }
+        } else if (a.kind == (int)WindowKind::Full) {
+            lo = 0;
+            hi = D - 1;
+        } else {
+            lo = max(d - a.bound, -(n - 1)) + n - 1;
+            hi = min(d + a.bound, n - 1) + n - 1;
+        }
+        wlo[r] = lo;
+        whi[r] = hi;
+    }
+
+    __syncthreads();
+    unsigned long long best = 0;
+    for (int i = k - 1; i >= 0; --i) {
+        const PixT* pix = img + (size_t)i * n * w;  // the band's pixels
+        // line sums of the cells the DP uses; lanes along x, waves along the
+        // rows (no division per cell; a row's base offset y * w is uniform)
+        for (int x = cx; x < w; x += 64) {
+            for (int r = ry; r < D; r += kRowLanes) {
+                const int d = r - (n - 1);
+                const int s = d < 0 ? -d : d;
+                int sum = 0;
+                if ((unsigned)(x + d) < (unsigned)w) {
+                    const unsigned char* o = off + s * n;
+                    if (d >= 0) {
+#pragma unroll
+                        for (int y = 0; y < N; ++y) sum += (int)pix[y * w + x + o[y]];
+                    } else {
+#pragma unroll
+                        for (int y = 0; y < N; ++y) sum += (int)pix[y * w + x - o[y]];
+                    }
+                }
+                H[r * w + x] = sum;
+            }
+        }
+        __syncthreads();
+        // V_i from V_{i+1} (eqs. (3)-(4)); V_{k-1} is the masked table
+        for (int x = cx; x < w; x += 64) {
+            for (int r = ry; r < D; r += kRowLanes) {
+                const int c = r * w + x;
+                const int xp = x + r - (n - 1);
+                const bool valid = (unsigned)xp < (unsigned)w;
+                int val = -1;
+                if (i == k - 1) {
+                    val = valid ? H[c] : -1;
+                } else if (valid) {
+                    // ascending rows, four reads in flight; a later row wins only
+                    // when larger (-2: below every value, -1 marks a missing cell)
+                    const int lo = wlo[r], hi = whi[r];
+                    int m = -2, ia = lo;
+                    for (int r0 = lo; r0 <= hi; r0 += 4) {
+                        int v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            v[u] = r0 + u <= hi ? Vp[(r0 + u) * w + xp] : -2;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const bool take = v[u] > m;
+                            m = take ? v[u] : m;
+                            ia = take ? r0 + u : ia;
+                        }
+                    }
+                    val = m >= 0 ? H[c] + m : -1;
+                    A[(size_t)i * cells + (size_t)r * w + xp] = (unsigned char)ia;
+                }
+                if (i == 0) {
+                    if (valid) {
+                        const unsigned long long kk = small_key(val, x, r, D);
+                        best = kk > best ? kk : best;
+                    }
+                } else {
+                    Vc[c] = val;
+                }
+            }
+        }
+        __syncthreads();
+        int* tmp = Vp;
+        Vp = Vc;
+        Vc = tmp;
+    }
+    // the best key of the workgroup: wave maxima, then one thread
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long v = __shfl_xor(best, o, 64);
+        best = v > best ? v : best;
+    }
+    if ((t & 63) == 0) part[t >> 6] = best;
+    __syncthreads();
+    if (t != 0) return;
+    unsigned long long kv = part[0];
+    for (int q = 1; q < kSmallThreads / 64; ++q) kv = part[q] > kv ? part[q] : kv;
+    const unsigned int lin = 0xffffffffu - (unsigned int)(kv & 0xffffffffull);
+    if ((kv >> 32) == 0 || lin / (unsigned int)D >= (unsigned int)w) {
+        *a.score = -1;
+        return;
+    }
+    int x = (int)(lin / (unsigned int)D), r = (int)(lin % (unsigned int)D);
+    a.xs[0] = x;
+    for (int i = 0; i + 1 < k; ++i) {
+        x += r - (n - 1);  // x_{i+1}
+        a.xs[i + 1] = x;
+        r = A[(size_t)i * cells + (size_t)r * w + x];
+    }
+    a.xs[k] = x + r - (n - 1);
+    *a.score = (int)(kv >> 32) - 1;
+}
+
+constexpr int kMaxDevices = 64;
+
+// The kernel's dynamic LDS limit, raised once per device (the attribute is
+// a property of the function on the current device).
+template <typename PixT, int N, int CAP>
+hipError_t allow_lds() {
+    static std::once_flag once[kMaxDevices];
+    static hipError_t rc[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return hipErrorInvalidDevice;
+    }
+    std::call_once(once[dev], [&] {
+        rc[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&detect_small<PixT, N, CAP>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLds);
+    });
+    return rc[dev];
+}
+
+template <typename PixT, int N, int CAP>
+hipError_t launch_small_n(const SmallPack<CAP>& pk, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds<PixT, N, CAP>();
+    if (e != hipSuccess) return e;
+    TimedLaunch tl("detect_small", s);
+    hipLaunchKernelGGL((detect_small<PixT, N, CAP>), dim3(pk.count), dim3(kSmallThreads), lds, s,
+                       pk);
+    return hipGetLastError();
+}
+
+template <typename PixT, int CAP>
+hipError_t launch_small_t(int n, const SmallPack<CAP>& pk, size_t lds, hipStream_t s) {
+    switch (n) {
+        case 1: return launch_small_n<PixT, 1, CAP>(pk, lds, s);
+        case 2: return launch_small_n<PixT, 2, CAP>(pk, lds, s);
+        case 4: return launch_small_n<PixT, 4, CAP>(pk, lds, s);
+        case 8: return launch_small_n<PixT, 8, CAP>(pk, lds, s);
+        case 16: return launch_small_n<PixT, 16, CAP>(pk, lds, s);
+        case 32: return launch_small_n<PixT, 32, CAP>(pk, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool small_apply(const Geometry& g, int dtype, const DpPlan& pl, Pin pin, bool alone) {
+    if (!pl.small || pin.j >= 0 || g.n > kSmallMaxN ||
+        small_lds_bytes(g.n, g.w, g.k, dtype == 0 ? 1 : 2) > kSmallLds)
+        return false;
+    // One image alone runs on one CU, bound by its LDS reads (about n + 8 per
+    // cell and band; 1.7 + 1.1 us per band at 64 x 64, k = 4), while the
+    // general path costs a few launches whatever the size: take the
+    // one-workgroup path while its work stays below about 1.25 times that of
+    // the 64 x 64 image (4 bands x 31 x 64 cells x 24).  In a batch the
+    // images run side by side on separate CUs.
+    const long long work = (long long)g.k * g.D * g.w * (g.n + 8);
+    return !alone || work <= 240000;
+}
+
+hipError_t launch_small_jobs(const SmallJobSpec* jobs, int count, hipStream_t s) {
+    // packs of one pixel type and band height
+    for (int dtype = 0; dtype < 2; ++dtype)
+    for (int n = 1; n <= kSmallMaxN; n *= 2) {
+        std::vector<const SmallJobSpec*> group;
+        for (int q = 0; q < count; ++q)
+            if (jobs[q].dtype == dtype && jobs[q].g.n == n) group.push_back(&jobs[q]);
+        for (size_t q0 = 0; q0 < group.size(); q0 += kSmallPack) {
+            const int cnt = (int)std::min<size_t>(kSmallPack, group.size() - q0);
+            size_t lds = 0;
+            auto fill = [&](SmallJob& j, const SmallJobSpec& J) {
+                j.img = J.img;
+                j.score = J.score;
+                j.xs = J.xs;
+                j.h = J.g.h;
+                j.w = J.g.w;
+                j.k = J.g.k;
+                j.n = J.g.n;
+                j.kind = (int)J.plan.kind;
+                j.bound = J.plan.bound;
+                j.tan_g = J.plan.tan_gamma;
+                lds = std::max(lds, small_lds_bytes(J.g.n, J.g.w, J.g.k, dtype == 0 ? 1 : 2));
+            };
+            hipError_t e;
+            if (cnt == 1) {
+                SmallPack<1> pk{};
+                fill(pk.job[0], *group[q0]);
+                pk.count = 1;
+                e = dtype == 0 ? launch_small_t<uint8_t, 1>(n, pk, lds, s)
+                               : launch_small_t<uint16_t, 1>(n, pk, lds, s);
+            } else {
+                SmallPack<kSmallPack> pk{};
+                for (int q = 0; q < cnt; ++q) fill(pk.job[q], *group[q0 + q]);
+                pk.count = cnt;
+                e = dtype == 0 ? launch_small_t<uint8_t, kSmallPack>(n, pk, lds, s)
+                               : launch_small_t<uint16_t, kSmallPack>(n, pk, lds, s);
+            }
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace fhtp

@@ -68,7 +68,8 @@ class TuneRule(C.Structure):
 
     _fields_ = [("dtype", C.c_int32), ("log2n", C.c_int32), ("w_min", C.c_int32),
                 ("w_max", C.c_int32), ("window", C.c_int32), ("dc", C.c_int32),
-                ("steps", C.c_int32), ("stripe", C.c_int32), ("fht_grid", C.c_int32)]
+                ("steps", C.c_int32), ("stripe", C.c_int32), ("fht_grid", C.c_int32),
+                ("small", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

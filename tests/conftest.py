@@ -17,3 +17,15 @@ def pytest_configure(config):
 def orc():
     import oracle
     return oracle.lib()
+
+
+@pytest.fixture(params=["fused", "general"])
+def path(request):
+    """GPU tests taking this fixture run twice: with the library's defaults (small
+    images take the one-workgroup path) and with the general kernels only."""
+    if request.param == "general":
+        from tests.gpu_util import general_path
+        with general_path():
+            yield request.param
+    else:
+        yield request.param

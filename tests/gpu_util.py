@@ -2,6 +2,7 @@
 
 from __future__ import annotations
 
+import contextlib
 import sys
 
 import numpy as np
@@ -28,3 +29,16 @@ def to_device(img: np.ndarray, dev):
 
 def host(t) -> np.ndarray:
     return t.detach().cpu().numpy()
+
+
+@contextlib.contextmanager
+def general_path():
+    """Run with the general kernels only: small images do not take the
+    one-workgroup path (a tuning rule; the rules in force are restored)."""
+    from paper_1912_01884_amd import autotune, fhtp
+    previous = fhtp.tune_get()
+    fhtp.tune_set([autotune.rule(small=1)])
+    try:
+        yield
+    finally:
+        fhtp.tune_set(previous)

@@ -28,7 +28,7 @@ def test_rules_round_trip_and_clear():
     assert fhtp.tune_get() == []
 
 
-@pytest.mark.parametrize("bad", [dict(dc=12), dict(steps=4), dict(steps=-1), dict(stripe=65), dict(stripe=-1),
+@pytest.mark.parametrize("bad", [dict(dc=12), dict(steps=4), dict(steps=-1), dict(small=2), dict(small=-1), dict(stripe=65), dict(stripe=-1),
                                  dict(fht_grid=2), dict(window=2), dict(dtype=3), dict(log2n=11),
                                  dict(w_min=5, w_max=4), dict(w_min=-1)])
 def test_out_of_range_rules_are_refused_and_change_nothing(bad):

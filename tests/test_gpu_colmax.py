@@ -62,7 +62,7 @@ def F():
 
 @pytest.mark.parametrize("kind", ["random", "ties", "zero"])
 @pytest.mark.parametrize("h,w,k,dt", SHAPES, ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in SHAPES])
-def test_unbounded_bend(dev, F, orc, h, w, k, dt, kind):
+def test_unbounded_bend(dev, F, orc, h, w, k, dt, kind, path):
     img = _img(h, w, dt, 13 * h + w + k, kind)
     n = h // k
     want_s, want_x = orc.detect_polyline(img, k, bend=2 * n - 2)
@@ -84,7 +84,7 @@ def test_unbounded_full_size(dev, F, orc):
     assert host(xs).tolist() == want_x.tolist()
 
 
-def test_unbounded_batch(dev, F, orc):
+def test_unbounded_batch(dev, F, orc, path):
     """One batch mixing unbounded images of several shapes with fixed and
     scanned windows: every result equals the oracle's."""
     jobs = []

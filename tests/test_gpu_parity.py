@@ -14,7 +14,7 @@ import pytest
 import torch  # noqa: F401  (imported at collection, outside per-test time limits)
 
 import synth
-from tests.gpu_util import announce, host, require_gpu, to_device
+from tests.gpu_util import announce, general_path, host, require_gpu, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -97,7 +97,7 @@ def test_detect_configs(dev, F, orc, cfg):
 
 
 @pytest.mark.parametrize("B", [0, 1, 2, 5, 8, 16, 17, 29, 30, 100])
-def test_detect_c1_every_window_kind(dev, F, orc, B):
+def test_detect_c1_every_window_kind(dev, F, orc, B, path):
     s = synth.make_small()
     want_s, want_x = orc.detect_polyline(s.image, s.k, bend=B)
     announce(f"detect 64x64 B={B}")
@@ -107,7 +107,7 @@ def test_detect_c1_every_window_kind(dev, F, orc, B):
 
 
 @pytest.mark.parametrize("gamma", [0.0, 0.05, 0.2, math.radians(10), 1.0, math.pi / 2, 2.0])
-def test_detect_angle_bound(dev, F, orc, gamma):
+def test_detect_angle_bound(dev, F, orc, gamma, path):
     for cfg in ("64x64", "1024x1024"):
         s = synth.make_config(cfg)
         want_s, want_x = orc.detect_polyline(s.image, s.k, gamma=gamma)
@@ -150,7 +150,7 @@ EDGE = [
 
 @pytest.mark.parametrize("h,w,k,dtype,maxval,B", EDGE,
                          ids=[f"{c[0]}x{c[1]}k{c[2]}B{c[5]}" for c in EDGE])
-def test_detect_edges(dev, F, orc, h, w, k, dtype, maxval, B):
+def test_detect_edges(dev, F, orc, h, w, k, dtype, maxval, B, path):
     img = _img(h, w, dtype, 7 * h + w, maxval)
     want_s, want_x = orc.detect_polyline(img, k, bend=B)
     announce(f"detect edge {h}x{w} k={k} B={B}")
@@ -178,7 +178,8 @@ def test_detect_paired_steps(dev, F, orc, h, w, k, B):
     img = _img(h, w, np.uint8, 31 * h + w + B, 3 if B % 2 == 0 else None)
     want_s, want_x = orc.detect_polyline(img, k, bend=B)
     announce(f"detect paired {h}x{w} k={k} B={B}")
-    sc, xs = F.detect_polyline(to_device(img, dev), k, bend=B)
+    with general_path():  # the two-step kernel, also where the image is small
+        sc, xs = F.detect_polyline(to_device(img, dev), k, bend=B)
     assert int(host(sc)[0]) == want_s
     assert host(xs).tolist() == want_x.tolist()
 
@@ -213,7 +214,7 @@ def test_saturated_image(dev, F, orc):
 
 
 @pytest.mark.parametrize("seed", range(12))
-def test_detect_random_tiny(dev, F, orc, seed):
+def test_detect_random_tiny(dev, F, orc, seed, path):
     rng = _rng(500 + seed)
     n = int(rng.choice([1, 2, 4, 8, 16]))
     k = int(rng.integers(1, 6))

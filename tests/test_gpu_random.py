@@ -37,18 +37,18 @@ def _cases(count, seed):
 
 
 @pytest.mark.parametrize("seed", [0, 1])
-def test_random_single_detections(orc, seed):
+def test_random_single_detections(orc, seed, path):
     dev = require_gpu()
     for q, (img, k, kw) in enumerate(_cases(100, seed)):
         want_s, want_x = orc.detect_polyline(img, k, **kw)
-        announce(f"random {seed}/{q}: {img.shape} {img.dtype} k={k} {kw}")
+        announce(f"random {seed}/{q} ({path}): {img.shape} {img.dtype} k={k} {kw}")
         from paper_1912_01884_amd import fhtp
         sc, xs = fhtp.detect_polyline(to_device(img, dev), k, **kw)
         assert int(host(sc)[0]) == want_s, (q, img.shape, k, kw)
         assert host(xs).tolist() == want_x.tolist(), (q, img.shape, k, kw)
 
 
-def test_random_batches(orc):
+def test_random_batches(orc, path):
     from paper_1912_01884_amd import fhtp
     dev = require_gpu()
     rng = np.random.default_rng([191201884, 4243])

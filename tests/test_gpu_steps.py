@@ -46,7 +46,7 @@ def _img(h, w, dtype, seed):
 
 def _steps_rule(steps):
     from paper_1912_01884_amd import autotune
-    return [autotune.rule(window=0, dc=8, steps=steps)]
+    return [autotune.rule(window=0, dc=8, steps=steps, small=1)]
 
 
 @pytest.fixture(scope="module")

@@ -57,7 +57,7 @@ def F():
 
 @pytest.mark.parametrize("ties", [False, True])
 @pytest.mark.parametrize("h,w,k,dt", SHAPES, ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in SHAPES])
-def test_angle_windows(dev, F, orc, h, w, k, dt, ties):
+def test_angle_windows(dev, F, orc, h, w, k, dt, ties, path):
     img = _img(h, w, dt, 7 * h + w + k + ties, ties)
     d = to_device(img, dev)
     for g in GAMMAS:
@@ -69,7 +69,7 @@ def test_angle_windows(dev, F, orc, h, w, k, dt, ties):
 
 
 @pytest.mark.parametrize("h,w,k,dt", SHAPES, ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in SHAPES])
-def test_large_bounds(dev, F, orc, h, w, k, dt):
+def test_large_bounds(dev, F, orc, h, w, k, dt, path):
     n = h // k
     img = _img(h, w, dt, 11 * h + w, False)
     d = to_device(img, dev)
@@ -81,7 +81,7 @@ def test_large_bounds(dev, F, orc, h, w, k, dt):
         assert host(xs).tolist() == want_x.tolist(), B
 
 
-def test_windows_in_batches(dev, F, orc):
+def test_windows_in_batches(dev, F, orc, path):
     """Images of different band counts and heights in one pack: images at
     their last step take the scanning kernel in the same step as others on
     the block kernel."""
