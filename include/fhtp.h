@@ -61,7 +61,15 @@ extern "C" {
 #endif
 
 /* Pixel types of the input image. */
-typedef enum { FHTP_U8 = 0, FHTP_U16 = 1 } fhtp_dtype;
+typedef enum {
+    FHTP_U8 = 0,
+    FHTP_U16 = 1,
+    /* Not pixel types: these two give the enumeration the whole int32 range,
+     * so that any int a caller passes is a defined value in C++ as well as C,
+     * which the library then rejects with FHTP_ERR_DTYPE. */
+    FHTP_DTYPE_RANGE_MIN_ = -2147483647 - 1,
+    FHTP_DTYPE_RANGE_MAX_ = 2147483647
+} fhtp_dtype;
 
 /* Bend restriction between adjacent links (Section 2.3).
  * mode 0: |d_{i+1} - d_i| <= shift_bound (shift_bound >= 0; gamma_rad ignored).
