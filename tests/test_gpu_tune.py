@@ -8,6 +8,7 @@ stripes), and every score and vertex list must equal the CPU oracle's.  Then
 the tuner itself runs on a slice of the mixed-size workload.
 """
 
+import dataclasses
 import math
 
 import numpy as np
@@ -77,7 +78,13 @@ def test_tuner_on_mixed_workload_slice(tmp_path):
     res = autotune.tune(imgs, [s.k for s in batch], bends=[s.bend for s in batch], reps=2,
                         install_result=False)
     assert fhtp.tune_get() == []  # restored
-    assert res.rules and res.tuned_ms > 0 and res.default_ms > 0
+    assert 0 < res.tuned_ms <= res.default_ms
+    if not res.rules:
+        # No candidate beat the library's own choices within the timing noise:
+        # the tuner then keeps them (no rules).  Persistence and the tuned batch
+        # below are checked on rules that change every launch shape instead.
+        assert res.tuned_ms == res.default_ms
+        res = dataclasses.replace(res, rules=[autotune.rule(steps=1, dc=16, stripe=4, fht_grid=1)])
     assert len(res.timings) == 1 + len(autotune.DP_CANDIDATES) + 2 * len(
         {(0, (s.h // s.k).bit_length() - 1) for s in batch})
     path = str(tmp_path / "plan.json")
