@@ -15,7 +15,10 @@
 // same value as the stage recursion.  The dyadic offsets come from the
 // recursive definition: the upper half of the line with shift s over n rows
 // is the line with shift floor(s/2) over n/2 rows, the lower half the same
-// line moved right by ceil(s/2); left-leaning lines mirror it.  Window maxima
+// line moved right by ceil(s/2); left-leaning lines mirror it.  Unrolled over
+// the rows, the offset of row y is the sum, over the set bits l-1 of y, of
+// ceil(s_l / 2), s_l being the shift at level l: a handful of scalar adds per
+// line, since a wave's lanes share the shift.  Window maxima
 // are scanned in ascending row order (ties to the smallest d'), the keys pick
 // the largest value with the smallest (x, d), and the walk follows the
 // back-pointers held in LDS: the same result as the general path, bit for
@@ -54,12 +57,12 @@ struct SmallPack {
 
 __host__ __device__ inline size_t align4(size_t b) { return (b + 3) & ~size_t(3); }
 
-// LDS bytes of one image: its pixels, the dyadic offsets, a band's line sums
-// and two value planes, the back-pointers of every step, windows.
+// LDS bytes of one image: its pixels, a band's line sums and two value
+// planes, the back-pointers of every step, windows.
 size_t small_lds_bytes(int n, int w, int k, int bpp) {
     const size_t D = 2 * (size_t)n - 1;
-    return (kSmallThreads / 64) * 8 + align4((size_t)n * k * w * bpp) + align4((size_t)n * n) +
-           3 * D * w * 4 + align4((size_t)(k > 1 ? k - 1 : 0) * D * w) + 2 * D * 4;
+    return (kSmallThreads / 64) * 8 + align4((size_t)n * k * w * bpp) + 3 * D * w * 4 +
+           align4((size_t)(k > 1 ? k - 1 : 0) * D * w) + 2 * D * 4;
 }
 
 __device__ __forceinline__ unsigned long long small_key(int val, int x, int r, int D) {
@@ -79,13 +82,14 @@ __global__ __launch_bounds__(kSmallThreads) void detect_small(SmallPack<CAP> pk)
     const int t = threadIdx.x;
     const int cells = D * w;
     constexpr int kRowLanes = kSmallThreads / 64;
-    const int cx = t & 63, ry = t >> 6;  // column lane, row lane
+    constexpr int kRowsPer = (D + kRowLanes - 1) / kRowLanes;  // rows per row lane
+    // column lane, and row lane (uniform across a wave: its rows, shifts and
+    // windows live in scalar registers)
+    const int cx = t & 63, ry = __builtin_amdgcn_readfirstlane(t >> 6);
     unsigned long long* part = small_lds;  // one key per wave
     char* base = reinterpret_cast<char*>(small_lds + kSmallThreads / 64);
     PixT* img = reinterpret_cast<PixT*>(base);  // the whole image
     base += align4((size_t)n * k * w * sizeof(PixT));
-    unsigned char* off = reinterpret_cast<unsigned char*>(base);  // off[s * n + y]
-    base += align4((size_t)n * n);
     int* H = reinterpret_cast<int*>(base);
     int* Vp = H + cells;      // values of the band below (V_{i+1})
     int* Vc = Vp + cells;     // values of this band (V_i)
@@ -134,20 +138,6 @@ __global__ __launch_bounds__(kSmallThreads) void detect_small(SmallPack<CAP> pk)
             }
         }
     }
-    // dyadic offsets D_s(y), s, y in [0, n): a row's bits from the top level down
-    constexpr int p = N >= 32 ? 5 : N >= 16 ? 4 : N >= 8 ? 3 : N >= 4 ? 2 : N >= 2 ? 1 : 0;
-    for (int q = t; q < n * n; q += kSmallThreads) {
-        int s = q / n, y = q - (q / n) * n, o = 0;
-        for (int l = p; l >= 1; --l) {
-            const int half = 1 << (l - 1);
-            if (y >= half) {
-                o += (s + 1) >> 1;
-                y -= half;
-            }
-            s >>= 1;
-        }
-        off[q] = (unsigned char)o;
-    }
     // windows [lo, hi] of every displacement, as rows
     for (int r = t; r < D; r += kSmallThreads) {
         const int d = r - (n - 1);
@@ -176,24 +166,42 @@ __global__ __launch_bounds__(kSmallThreads) void detect_small(SmallPack<CAP> pk)
     }
 
     __syncthreads();
+    // the windows of the thread's rows ry, ry + kRowLanes, ...
+    int wl[kRowsPer], wh[kRowsPer];
+#pragma unroll
+    for (int q = 0; q < kRowsPer; ++q) {
+        const int r = ry + q * kRowLanes;
+        wl[q] = r < D ? wlo[r] : 0;
+        wh[q] = r < D ? whi[r] : -1;
+    }
+    constexpr int p = N >= 32 ? 5 : N >= 16 ? 4 : N >= 8 ? 3 : N >= 4 ? 2 : N >= 2 ? 1 : 0;
     unsigned long long best = 0;
     for (int i = k - 1; i >= 0; --i) {
         const PixT* pix = img + (size_t)i * n * w;  // the band's pixels
         // line sums of the cells the DP uses; lanes along x, waves along the
-        // rows (no division per cell; a row's base offset y * w is uniform)
+        // rows (a row's shift, its offsets and y * w are uniform)
         for (int x = cx; x < w; x += 64) {
-            for (int r = ry; r < D; r += kRowLanes) {
+#pragma unroll
+            for (int q = 0; q < kRowsPer; ++q) {
+                const int r = ry + q * kRowLanes;
+                if (r >= D) break;
                 const int d = r - (n - 1);
+                const int sg = d < 0 ? -1 : 1;
                 const int s = d < 0 ? -d : d;
+                // c[l] = ceil(s_l / 2), s_l = s >> (p - l): what level l adds
+                // to the offset of a row whose bit l-1 is set
+                int c[p + 1];
+#pragma unroll
+                for (int l = 1; l <= p; ++l) c[l] = ((s >> (p - l)) + 1) >> 1;
                 int sum = 0;
                 if ((unsigned)(x + d) < (unsigned)w) {
-                    const unsigned char* o = off + s * n;
-                    if (d >= 0) {
 #pragma unroll
-                        for (int y = 0; y < N; ++y) sum += (int)pix[y * w + x + o[y]];
-                    } else {
+                    for (int y = 0; y < N; ++y) {
+                        int o = 0;
 #pragma unroll
-                        for (int y = 0; y < N; ++y) sum += (int)pix[y * w + x - o[y]];
+                        for (int l = 1; l <= p; ++l)
+                            if ((y >> (l - 1)) & 1) o += c[l];
+                        sum += (int)pix[y * w + x + sg * o];
                     }
                 }
                 H[r * w + x] = sum;
@@ -202,7 +210,10 @@ __global__ __launch_bounds__(kSmallThreads) void detect_small(SmallPack<CAP> pk)
         __syncthreads();
         // V_i from V_{i+1} (eqs. (3)-(4)); V_{k-1} is the masked table
         for (int x = cx; x < w; x += 64) {
-            for (int r = ry; r < D; r += kRowLanes) {
+#pragma unroll
+            for (int q = 0; q < kRowsPer; ++q) {
+                const int r = ry + q * kRowLanes;
+                if (r >= D) break;
                 const int c = r * w + x;
                 const int xp = x + r - (n - 1);
                 const bool valid = (unsigned)xp < (unsigned)w;
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(kSmallThreads) void detect_small(SmallPack<CAP> pk)
                 } else if (valid) {
                     // ascending rows, four reads in flight; a later row wins only
                     // when larger (-2: below every value, -1 marks a missing cell)
-                    const int lo = wlo[r], hi = whi[r];
+                    const int lo = wl[q], hi = wh[q];
                     int m = -2, ia = lo;
                     for (int r0 = lo; r0 <= hi; r0 += 4) {
                         int v[4];
