@@ -55,7 +55,7 @@ class Request:
     score: Any = None             # device int32[1], written by the detection
     xs: Any = None                # device int32[k+1]
     rid: int = -1
-    arrival: float = math.nan     # seconds on the driver's clock
+    arrival: float = math.nan     # seconds on the load generator's clock
     admitted: float = math.nan
     done: float = math.nan
     nbytes: int = 0               # arena bytes while in flight
