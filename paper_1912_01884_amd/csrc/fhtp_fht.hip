@@ -164,6 +164,11 @@ __device__ __forceinline__ void fht_stage_free(int32_t (&v)[N], int32_t* lds, in
             v[b * 2 * half + 2 * t] = a + x;
         }
     }
+    // The stage's sums are final here.  Integer adds reassociate freely, and
+    // without this the compiler carried partial sums of several stages at once
+    // (at n = 128 with 16-bit pixels: 256 VGPRs and 6 spilled; pinned: 188).
+#pragma unroll
+    for (int q = 0; q < N; ++q) asm volatile("" : "+v"(v[q]));
 }
 
 template <int N, int J, int P, int RW, bool GROUPED>
@@ -188,6 +193,8 @@ __device__ __forceinline__ void fht_stages(int32_t (&v)[N], int32_t* lds, int co
 #pragma unroll
             for (int q = 0; q < 2 * half; ++q) v[b * 2 * half + q] = o[q];
         }
+#pragma unroll
+        for (int q = 0; q < N; ++q) asm volatile("" : "+v"(v[q]));  // as after an LDS stage
         fht_stages<N, J + 1, P, RW, GROUPED>(v, lds, col, wcol);
     } else if constexpr (J <= P) {
         if constexpr (GROUPED)
@@ -280,12 +287,18 @@ __device__ __forceinline__ void fetch_column(const FhtJob& J, int local, int col
     const __amdgpu_buffer_rsrc_t r =
         make_rsrc(img + (size_t)it.blk * N * (size_t)J.w, (unsigned int)N * row_bytes);
     const unsigned int voff = (it.inside ? (unsigned int)it.ximg : 0u) * sizeof(PixT);
+    // Row offsets advance in one scalar register that the optimiser cannot
+    // precompute: it had hoisted every row's offset (of loads and of stores)
+    // out of the item loop into scalar registers, and spilled them.
+    unsigned int so = 0;
 #pragma unroll
     for (int q = 0; q < NPK; ++q) {
-        const uint32_t lo = buffer_pixel<PixT>(r, voff, (unsigned int)(2 * q) * row_bytes);
+        const uint32_t lo = buffer_pixel<PixT>(r, voff, so);
         uint32_t hi = 0u;
-        if constexpr (N > 1) hi = buffer_pixel<PixT>(r, voff, (unsigned int)(2 * q + 1) * row_bytes);
+        if constexpr (N > 1) hi = buffer_pixel<PixT>(r, voff, so + row_bytes);
         pk[q] = it.inside ? (lo | (hi << 16)) : 0u;
+        so += 2 * row_bytes;
+        asm volatile("" : "+s"(so));
     }
 }
 
@@ -300,8 +313,13 @@ __device__ __forceinline__ void fetch_column_direct(const FhtJob& J, int local, 
         make_rsrc(img + (size_t)it.blk * N * (size_t)J.w, (unsigned int)N * row_bytes);
     // Lanes past the image read beyond the buffer extent, which returns 0.
     const unsigned int voff = it.inside ? (unsigned int)it.ximg * sizeof(PixT) : 0x80000000u;
+    unsigned int so = 0;
 #pragma unroll
-    for (int y = 0; y < N; ++y) v[y] = (int32_t)buffer_pixel<PixT>(r, voff, (unsigned int)y * row_bytes);
+    for (int y = 0; y < N; ++y) {
+        v[y] = (int32_t)buffer_pixel<PixT>(r, voff, so);
+        so += row_bytes;
+        asm volatile("" : "+s"(so));
+    }
 }
 
 // Output modes of a run:
@@ -324,15 +342,21 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
         const __amdgpu_buffer_rsrc_t r =
             make_rsrc(J.out16 + (size_t)it.blk * D * (size_t)W, (unsigned int)D * row16);
         if (it.dir == 0) {
+            unsigned int so = (unsigned int)(N - 1) * row16;
 #pragma unroll
-            for (int s = 0; s < N; ++s)
-                __builtin_amdgcn_raw_buffer_store_b16(
-                    (unsigned short)v[s], r, (int)voff, (int)((unsigned int)(N - 1 + s) * row16), 0);
+            for (int s = 0; s < N; ++s) {
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v[s], r, (int)voff, (int)so, 0);
+                so += row16;
+                asm volatile("" : "+s"(so));
+            }
         } else {
+            unsigned int so = (unsigned int)(N - 2) * row16;
 #pragma unroll
-            for (int s = 1; s < N; ++s)
-                __builtin_amdgcn_raw_buffer_store_b16(
-                    (unsigned short)v[s], r, (int)voff, (int)((unsigned int)(N - 1 - s) * row16), 0);
+            for (int s = 1; s < N; ++s) {
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v[s], r, (int)voff, (int)so, 0);
+                so -= row16;
+                asm volatile("" : "+s"(so));
+            }
         }
     } else if (J.to_table) {
         constexpr int D = 2 * N - 1;
@@ -340,15 +364,21 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
         const __amdgpu_buffer_rsrc_t r = make_rsrc(
             J.out + (size_t)(it.blk - J.narrow) * D * (size_t)W, (unsigned int)D * row_bytes);
         if (it.dir == 0) {
+            unsigned int so = (unsigned int)(N - 1) * row_bytes;
 #pragma unroll
-            for (int s = 0; s < N; ++s)
-                __builtin_amdgcn_raw_buffer_store_b32(
-                    v[s], r, (int)voff, (int)((unsigned int)(N - 1 + s) * row_bytes), 0);
+            for (int s = 0; s < N; ++s) {
+                __builtin_amdgcn_raw_buffer_store_b32(v[s], r, (int)voff, (int)so, 0);
+                so += row_bytes;
+                asm volatile("" : "+s"(so));
+            }
         } else {
+            unsigned int so = (unsigned int)(N - 2) * row_bytes;
 #pragma unroll
-            for (int s = 1; s < N; ++s)
-                __builtin_amdgcn_raw_buffer_store_b32(
-                    v[s], r, (int)voff, (int)((unsigned int)(N - 1 - s) * row_bytes), 0);
+            for (int s = 1; s < N; ++s) {
+                __builtin_amdgcn_raw_buffer_store_b32(v[s], r, (int)voff, (int)so, 0);
+                so -= row_bytes;
+                asm volatile("" : "+s"(so));
+            }
         }
     } else if (J.sub16) {
         const unsigned int row16 = (unsigned int)W * 2u;
@@ -356,19 +386,25 @@ __device__ __forceinline__ void fht_store(const FhtJob& J, int local, int col,
             reinterpret_cast<uint16_t*>(J.out) + (size_t)(it.blk * C::NDIR + it.dir) * N * (size_t)W,
             (unsigned int)N * row16);
         const unsigned int voff = (unsigned int)it.c * 2u;
+        unsigned int so = 0;
 #pragma unroll
-        for (int s = 0; s < N; ++s)
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v[s], r, (int)voff,
-                                                  (int)((unsigned int)s * row16), 0);
+        for (int s = 0; s < N; ++s) {
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v[s], r, (int)voff, (int)so, 0);
+            so += row16;
+            asm volatile("" : "+s"(so));
+        }
     } else {
         const __amdgpu_buffer_rsrc_t r =
             make_rsrc(J.out + (size_t)(it.blk * C::NDIR + it.dir) * N * (size_t)W,
                       (unsigned int)N * row_bytes);
         const unsigned int voff = (unsigned int)it.c * 4u;
+        unsigned int so = 0;
 #pragma unroll
-        for (int s = 0; s < N; ++s)
-            __builtin_amdgcn_raw_buffer_store_b32(v[s], r, (int)voff,
-                                                  (int)((unsigned int)s * row_bytes), 0);
+        for (int s = 0; s < N; ++s) {
+            __builtin_amdgcn_raw_buffer_store_b32(v[s], r, (int)voff, (int)so, 0);
+            so += row_bytes;
+            asm volatile("" : "+s"(so));
+        }
     }
 }
 
