@@ -265,7 +265,7 @@ class FhtpBackend:
     """Arena in device memory, streams and events; groups run fhtp_detect_batch."""
 
     def __init__(self, device=None, arena_bytes: Optional[int] = None, streams: int = 4,
-                 free_fraction: float = 0.5):
+                 free_fraction: float = 0.5, warmup: bool = True):
         import torch
 
         from . import fhtp
@@ -288,6 +288,35 @@ class FhtpBackend:
         # event is re-recorded for each group instead of created anew
         self.events = [torch.cuda.Event() for _ in range(streams)]
         # the arena's allocation is ordered before any group on any stream
+        torch.cuda.synchronize(self.device)
+        if warmup:
+            self.warmup()
+
+    def warmup(self) -> None:
+        """Run one tiny batch on every stream before serving.
+
+        The batch mixes an image whose bands take the second-stream path (256
+        rows) with one that does not (64 rows), so the library creates the
+        second stream it keeps for each of this backend's streams now, and
+        loads its kernels, instead of during the first groups served (each
+        such first use stalls the host for milliseconds).
+        """
+        torch, F = self.torch, self.fhtp
+        imgs = [torch.zeros((256, 1), dtype=torch.uint8, device=self.device),
+                torch.zeros((64, 1), dtype=torch.uint8, device=self.device)]
+        scores = [torch.zeros(1, dtype=torch.int32, device=self.device) for _ in imgs]
+        xss = [torch.zeros(2, dtype=torch.int32, device=self.device) for _ in imgs]
+        jobs, _keep = F.make_jobs(imgs, [1, 1], bends=[0, 0], scores=scores, xss=xss)
+        nbytes = F.batch_workspace_bytes(jobs)
+        if nbytes > self.arena.numel():
+            return
+        arr = (F.Job * len(jobs))(*jobs)
+        for s in self.streams:
+            rc = self.L.fhtp_detect_batch(arr, len(jobs), C.c_void_p(self.base), nbytes,
+                                          C.c_void_p(s.cuda_stream))
+            F._check(rc, "detect_batch")
+            # the next stream's batch reuses the same arena bytes
+            s.synchronize()
         torch.cuda.synchronize(self.device)
 
     def capacity(self) -> int:
