@@ -290,3 +290,41 @@ def test_narrow_tables_at_the_bound(dev, F, orc, h, w, k, bend):
     sc, xs = F.detect_polyline(to_device(full, dev), k, bend=bend)
     assert int(host(sc)[0]) == 255 * h
     assert not host(xs).any()
+
+
+LONG = [
+    # (h, w, k, dtype): DP chains of hundreds of dependent steps (pair launches
+    # and walk trips by the hundred), bands of one to four rows
+    (2 * 1024, 37, 1024, np.uint8),   # n = 2: three displacements
+    (1024, 20, 1024, np.uint8),       # n = 1: one displacement, vertical links only
+    (4 * 600, 61, 600, np.uint16),    # n = 4
+]
+
+
+@pytest.mark.parametrize("h,w,k,dtype", LONG, ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in LONG])
+def test_long_chains(dev, F, orc, h, w, k, dtype, path):
+    n = h // k
+    img = _img(h, w, dtype, 5 * h + w, 3)
+    d = to_device(img, dev)
+    for kw in (dict(bend=0), dict(bend=1), dict(bend=2 * n - 2), dict(gamma=0.5)):
+        want_s, want_x = orc.detect_polyline(img, k, **kw)
+        announce(f"long chain {h}x{w} k={k} {kw}")
+        sc, xs = F.detect_polyline(d, k, **kw)
+        assert int(host(sc)[0]) == want_s, kw
+        assert host(xs).tolist() == want_x.tolist(), kw
+
+
+def test_long_chain_in_a_batch(dev, F, orc):
+    """A 1024-band image beside short ones in one batch: the images are aligned
+    at their last step, so the short ones sit out hundreds of launches."""
+    jobs = [(_img(2 * 1024, 37, np.uint8, 901, 3), 1024, 1),
+            (_img(64 * 3, 90, np.uint8, 902, None), 3, 1),
+            (_img(8 * 5, 50, np.uint8, 903, 3), 5, 2),
+            (_img(16 * 2, 200, np.uint16, 904, None), 2, 0)]
+    want = [orc.detect_polyline(img, k, bend=b) for img, k, b in jobs]
+    imgs = [to_device(img, dev) for img, _, _ in jobs]
+    announce("batch with a 1024-band image")
+    out = F.detect_batch(imgs, [j[1] for j in jobs], bends=[j[2] for j in jobs])
+    for q, (s, x) in enumerate(want):
+        assert int(host(out[q][0])[0]) == s, q
+        assert host(out[q][1]).tolist() == x.tolist(), q
