@@ -180,31 +180,89 @@ __global__ __launch_bounds__(kSmallThreads) void detect_small(SmallPack<CAP> pk)
         const PixT* pix = img + (size_t)i * n * w;  // the band's pixels
         // line sums of the cells the DP uses; lanes along x, waves along the
         // rows (a row's shift, its offsets and y * w are uniform)
-        for (int x = cx; x < w; x += 64) {
-#pragma unroll
-            for (int q = 0; q < kRowsPer; ++q) {
-                const int r = ry + q * kRowLanes;
-                if (r >= D) break;
-                const int d = r - (n - 1);
-                const int sg = d < 0 ? -1 : 1;
-                const int s = d < 0 ? -d : d;
-                // c[l] = ceil(s_l / 2), s_l = s >> (p - l): what level l adds
-                // to the offset of a row whose bit l-1 is set
-                int c[p + 1];
-#pragma unroll
-                for (int l = 1; l <= p; ++l) c[l] = ((s >> (p - l)) + 1) >> 1;
-                int sum = 0;
-                if ((unsigned)(x + d) < (unsigned)w) {
-#pragma unroll
-                    for (int y = 0; y < N; ++y) {
-                        int o = 0;
-#pragma unroll
-                        for (int l = 1; l <= p; ++l)
-                            if ((y >> (l - 1)) & 1) o += c[l];
-                        sum += (int)pix[y * w + x + sg * o];
-                    }
+        if constexpr (N >= 8) {
+            // Two levels of the recursion.  Every line of shift s crosses each
+            // block of 4 rows along the 4-row line of shift s2 = s >> (p - 2)
+            // (the levels below 4 rows see only the top bits of s), starting
+            // at the line's offset on the block's first row.  So the sums of
+            // the 4-row lines come first, per block m, shift s2 and direction
+            // (j < 4: right-leaning s2 = j; j >= 4: left-leaning s2 = j - 3;
+            // shift 0 is shared), in the plane of this band's values, which is
+            // free until the DP step: 7n/4 * w ints, within its (2n-1) * w.
+            constexpr int NB4 = N / 4;
+            int* P = Vc;
+            for (int x = cx; x < w; x += 64) {
+                for (int cq = ry; cq < NB4 * 7; cq += kRowLanes) {
+                    const int m = cq / 7, j = cq - m * 7;
+                    const bool right = j < 4;
+                    const int s2 = right ? j : j - 3;
+                    const int o1 = ((s2 >> 1) + 1) >> 1, o2 = (s2 + 1) >> 1;  // rows 1, 2
+                    const PixT* row = pix + (size_t)(4 * m) * w;
+                    // columns clamped into the band: such sums are never used
+                    auto px = [&](int t, int o) {
+                        const int xx = min(max(right ? x + o : x - o, 0), w - 1);
+                        return (int)row[t * w + xx];
+                    };
+                    P[cq * w + x] = px(0, 0) + px(1, o1) + px(2, o2) + px(3, o1 + o2);
                 }
-                H[r * w + x] = sum;
+            }
+            __syncthreads();
+            for (int x = cx; x < w; x += 64) {
+#pragma unroll
+                for (int q = 0; q < kRowsPer; ++q) {
+                    const int r = ry + q * kRowLanes;
+                    if (r >= D) break;
+                    const int d = r - (n - 1);
+                    const int s = d < 0 ? -d : d;
+                    const int s2 = s >> (p - 2);
+                    const int j = d >= 0 ? s2 : (s2 == 0 ? 0 : 3 + s2);
+                    // c[l] = ceil(s_l / 2), s_l = s >> (p - l), for the levels
+                    // above 4 rows: the offset of block m's first row is the sum
+                    // of c[l] over the set bits l-3 of m
+                    int c[p + 1];
+#pragma unroll
+                    for (int l = 3; l <= p; ++l) c[l] = ((s >> (p - l)) + 1) >> 1;
+                    int sum = 0;
+                    if ((unsigned)(x + d) < (unsigned)w) {
+#pragma unroll
+                        for (int m = 0; m < NB4; ++m) {
+                            int o = 0;
+#pragma unroll
+                            for (int l = 3; l <= p; ++l)
+                                if ((m >> (l - 3)) & 1) o += c[l];
+                            sum += P[(m * 7 + j) * w + x + (d < 0 ? -o : o)];
+                        }
+                    }
+                    H[r * w + x] = sum;
+                }
+            }
+        } else {
+            for (int x = cx; x < w; x += 64) {
+#pragma unroll
+                for (int q = 0; q < kRowsPer; ++q) {
+                    const int r = ry + q * kRowLanes;
+                    if (r >= D) break;
+                    const int d = r - (n - 1);
+                    const int sg = d < 0 ? -1 : 1;
+                    const int s = d < 0 ? -d : d;
+                    // c[l] = ceil(s_l / 2), s_l = s >> (p - l): what level l adds
+                    // to the offset of a row whose bit l-1 is set
+                    int c[p + 1];
+#pragma unroll
+                    for (int l = 1; l <= p; ++l) c[l] = ((s >> (p - l)) + 1) >> 1;
+                    int sum = 0;
+                    if ((unsigned)(x + d) < (unsigned)w) {
+#pragma unroll
+                        for (int y = 0; y < N; ++y) {
+                            int o = 0;
+#pragma unroll
+                            for (int l = 1; l <= p; ++l)
+                                if ((y >> (l - 1)) & 1) o += c[l];
+                            sum += (int)pix[y * w + x + sg * o];
+                        }
+                    }
+                    H[r * w + x] = sum;
+                }
             }
         }
         __syncthreads();

@@ -256,17 +256,19 @@ def _stream_ptr(stream) -> int:
     return int(s.cuda_stream)
 
 
-def _on_stream(stream):
+def _on_stream(stream, allocates: bool = True):
     """Context in which temporaries are allocated: the launch stream.
 
     torch's caching allocator hands a freed block only to later allocations
     on the stream it was allocated on, so a workspace or output allocated here
     and dropped after the call cannot be reused while the kernels enqueued on
-    `stream` still use it, whichever stream is current.
+    `stream` still use it, whichever stream is current.  A call that allocates
+    nothing (every buffer given) skips the switch, a few microseconds of host
+    time per call.
     """
     import contextlib
     torch = _torch()
-    if stream is None:
+    if stream is None or not allocates:
         return contextlib.nullcontext()
     return torch.cuda.stream(stream)
 
@@ -276,13 +278,16 @@ def _require_device(t, name: str):
         raise ValueError(f"{name} must be a contiguous device tensor")
 
 
-def _ws(nbytes: int, device, ws):
+def _ws(nbytes, device, ws):
+    """The workspace to pass: the caller's (the library checks its size), or a
+    new one of nbytes() bytes (none when that is 0)."""
     torch = _torch()
-    if nbytes == 0:
-        return None, 0
     if ws is not None:
         return ws, ws.numel() * ws.element_size()
-    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+    n = nbytes()
+    if n == 0:
+        return None, 0
+    return torch.empty(n, dtype=torch.uint8, device=device), n
 
 
 def _ptr(t) -> Optional[int]:
@@ -296,10 +301,10 @@ def fht_bands(img, k: int, tables=None, ws=None, stream=None):
     h, w = img.shape
     dt = _dtype_code(img)
     kk, D, W = table_shape(h, w, k)
-    with _on_stream(stream):
+    with _on_stream(stream, tables is None or ws is None):
         if tables is None:
             tables = torch.empty((kk, D, W), dtype=torch.int32, device=img.device)
-        ws_t, ws_n = _ws(fht_workspace_bytes(dt, h, w, k), img.device, ws)
+        ws_t, ws_n = _ws(lambda: fht_workspace_bytes(dt, h, w, k), img.device, ws)
         rc = lib().fhtp_fht_bands(img.data_ptr(), dt, h, w, k, tables.data_ptr(), _ptr(ws_t),
                                   ws_n, _stream_ptr(stream))
     _check(rc, "fht_bands")
@@ -312,12 +317,12 @@ def polyline_dp(tables, h: int, w: int, k: int, bend: Optional[int] = None,
     torch = _torch()
     _require_device(tables, "tables")
     b = make_bend(bend, gamma)
-    with _on_stream(stream):
+    with _on_stream(stream, score is None or xs is None or ws is None):
         if score is None:
             score = torch.empty(1, dtype=torch.int32, device=tables.device)
         if xs is None:
             xs = torch.empty(k + 1, dtype=torch.int32, device=tables.device)
-        ws_t, ws_n = _ws(dp_workspace_bytes(h, w, k, b), tables.device, ws)
+        ws_t, ws_n = _ws(lambda: dp_workspace_bytes(h, w, k, b), tables.device, ws)
         rc = lib().fhtp_polyline_dp(tables.data_ptr(), h, w, k, b, _ptr(ws_t), ws_n,
                                     score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
     _check(rc, "polyline_dp")
@@ -332,12 +337,12 @@ def detect_polyline(img, k: int, bend: Optional[int] = None, gamma: Optional[flo
     h, w = img.shape
     dt = _dtype_code(img)
     b = make_bend(bend, gamma)
-    with _on_stream(stream):
+    with _on_stream(stream, score is None or xs is None or ws is None):
         if score is None:
             score = torch.empty(1, dtype=torch.int32, device=img.device)
         if xs is None:
             xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
-        ws_t, ws_n = _ws(detect_workspace_bytes(dt, h, w, k, b), img.device, ws)
+        ws_t, ws_n = _ws(lambda: detect_workspace_bytes(dt, h, w, k, b), img.device, ws)
         rc = lib().fhtp_detect_polyline(img.data_ptr(), dt, h, w, k, b, _ptr(ws_t), ws_n,
                                         score.data_ptr(), xs.data_ptr(), _stream_ptr(stream))
     _check(rc, "detect_polyline")
@@ -402,7 +407,7 @@ def detect_polyline_ex(img, k: int, bend: Optional[int] = None, gamma: Optional[
             score = torch.empty(1, dtype=torch.int32, device=img.device)
         if xs is None:
             xs = torch.empty(k + 1, dtype=torch.int32, device=img.device)
-        ws_t, ws_n = _ws(detect_ex_workspace_bytes(dt, h, w, k, b, opt), img.device, ws)
+        ws_t, ws_n = _ws(lambda: detect_ex_workspace_bytes(dt, h, w, k, b, opt), img.device, ws)
         rc = lib().fhtp_detect_polyline_ex(img.data_ptr(), dt, h, w, k, b, C.byref(opt),
                                            _ptr(ws_t), ws_n, score.data_ptr(), xs.data_ptr(),
                                            _stream_ptr(stream))
@@ -444,7 +449,7 @@ def detect_batch(images, ks, bends=None, gammas=None, ws=None, scores=None, xss=
     with _on_stream(stream):
         jobs, keep = make_jobs(images, ks, bends, gammas, scores, xss)
         nbytes = batch_workspace_bytes(jobs)
-        ws_t, ws_n = _ws(nbytes, images[0].device, ws)
+        ws_t, ws_n = _ws(lambda: nbytes, images[0].device, ws)
         arr = (Job * len(jobs))(*jobs)
         rc = lib().fhtp_detect_batch(arr, len(jobs), _ptr(ws_t), ws_n, _stream_ptr(stream))
     _check(rc, "detect_batch")
@@ -467,7 +472,7 @@ class Plan:
             raise ValueError("a plan needs at least one image")
         jobs, keep = make_jobs(images, ks, bends, gammas, scores, xss)
         nbytes = batch_workspace_bytes(jobs)
-        ws_t, ws_n = _ws(nbytes, images[0].device, ws)
+        ws_t, ws_n = _ws(lambda: nbytes, images[0].device, ws)
         arr = (Job * len(jobs))(*jobs)
         h = C.c_void_p()
         _check(lib().fhtp_plan_create(arr, len(jobs), _ptr(ws_t), ws_n, C.byref(h)), "plan_create")
