@@ -9,10 +9,11 @@
 // FHT, one per one or two DP steps, the walk) are each a few microseconds of
 // launch latency around very little work.  Here a workgroup loads the image
 // into LDS once, then runs band by band from the bottom: the line sums H_i(x, d)
-// for the cells the DP uses (x in [0, w), x + d in [0, w)) summed directly
-// along the dyadic line, then the DP step on the previous band's values in
-// LDS.  Line sums are exact integers, so summing a line directly gives the
-// same value as the stage recursion.  The dyadic offsets come from the
+// for the cells the DP uses (x in [0, w), x + d in [0, w)) summed along the
+// dyadic line (pixel by pixel for bands of up to 4 rows, from sums over blocks
+// of 4 rows for taller ones), then the DP step on the previous band's values
+// in LDS.  Line sums are exact integers, so any grouping of a line's pixels
+// gives the same value as the stage recursion.  The dyadic offsets come from the
 // recursive definition: the upper half of the line with shift s over n rows
 // is the line with shift floor(s/2) over n/2 rows, the lower half the same
 // line moved right by ceil(s/2); left-leaning lines mirror it.  Unrolled over
