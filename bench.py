@@ -34,13 +34,13 @@ HBM_PEAK_GBPS = 8000.0
 TRAFFIC = {
     "fht_reg_kernel": {"source": "paper_1912_01884_amd/csrc/fhtp_fht.hip",
                       "source_sha256": "e7eee6e6575463104e02e08783cd3137e37f8275f260b872fb3e9b5f019fc535",
-                      "fetch_bytes": 36858825, "write_bytes": 142905696},
+                      "fetch_bytes": 36857074, "write_bytes": 142808608},
     "dp_pair_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
                      "source_sha256": "4149219b3c9bf6dc7417d146a744ebf62f492c8b091e440efef3a66ad3b0b50e",
-                     "fetch_bytes": 14002203, "write_bytes": 6653440},
+                     "fetch_bytes": 14002144, "write_bytes": 6653440},
     "dp_step_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
                      "source_sha256": "4149219b3c9bf6dc7417d146a744ebf62f492c8b091e440efef3a66ad3b0b50e",
-                     "fetch_bytes": 8697938, "write_bytes": 6144},
+                     "fetch_bytes": 8698173, "write_bytes": 6144},
     "walk": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
             "source_sha256": "4149219b3c9bf6dc7417d146a744ebf62f492c8b091e440efef3a66ad3b0b50e",
             "fetch_bytes": 138607, "write_bytes": 192},
