@@ -328,3 +328,15 @@ def test_long_chain_in_a_batch(dev, F, orc):
     for q, (s, x) in enumerate(want):
         assert int(host(out[q][0])[0]) == s, q
         assert host(out[q][1]).tolist() == x.tolist(), q
+
+
+def test_largest_image(dev, F, orc):
+    """16384 x 16384 uint16 with k = 128 bands of 128 rows (the largest image
+    of the sizes tested: 2.2 GB of band tables, 127 DP steps, offsets and
+    views at scale): the score and all 129 vertices equal the oracle's."""
+    s = synth.make_large(0, h=16384, w=16384, k=128)
+    want_s, want_x = orc.detect_polyline(s.image, s.k, bend=s.bend)
+    announce("detect 16384x16384 k=128 B=8")
+    sc, xs = F.detect_polyline(to_device(s.image, dev), s.k, bend=s.bend)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
