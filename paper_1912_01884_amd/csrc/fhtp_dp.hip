@@ -368,13 +368,81 @@ __device__ __forceinline__ void emit(const DpJob& a, const RowView& ov, const Ro
 }
 
 // Sliding maximum of the windows [j, j + 2B] of v, j = 0 .. DC-1, with the
-// smallest index reaching it (van Herk / Gil-Werman: suffix maxima and prefix
-// maxima inside blocks of the window length).
+// smallest index reaching it: each window is split at a block start b in
+// (j, j + 2B] into the suffix maximum of v[j .. b-1] within its block and the
+// prefix maximum of v[b .. j+2B] within the next (van Herk / Gil-Werman).
+// When DC <= 2B every window holds both v[DC-1] and v[DC], so the single
+// boundary b = DC serves them all; otherwise blocks of 2B start at multiples
+// of 2B, and b is the first one above j.  Only the suffixes that start below
+// DC and the prefixes that start at a boundary are formed (about two thirds
+// of the compares and selects of blocks of the window length over all of v).
+// Ties go to the smallest index: suffixes are taken descending on >=,
+// prefixes ascending on >, and the suffix (the smaller indices) wins a tie
+// between the two.
 template <int B, int DC>
 __device__ __forceinline__ void window_max(const int (&v)[DC + 2 * B], int (&m)[DC],
                                            int (&ia)[DC]) {
     constexpr int L = 2 * B + 1;
     constexpr int NV = DC + 2 * B;
+    if constexpr (DC <= 2 * B) {
+        int sv[DC], si[DC];
+        sv[DC - 1] = v[DC - 1];
+        si[DC - 1] = DC - 1;
+#pragma unroll
+        for (int q = DC - 2; q >= 0; --q) {
+            const bool take = v[q] >= sv[q + 1];
+            sv[q] = take ? v[q] : sv[q + 1];
+            si[q] = take ? q : si[q + 1];
+        }
+        int pv = v[DC], pi = DC;
+#pragma unroll
+        for (int t = DC; t < NV; ++t) {
+            if (t > DC && v[t] > pv) {
+                pv = v[t];
+                pi = t;
+            }
+            const int j = t - 2 * B;  // the window ending at t
+            if (j >= 0 && j < DC) {
+                const bool s_wins = sv[j] >= pv;
+                m[j] = s_wins ? sv[j] : pv;
+                ia[j] = s_wins ? si[j] : pi;
+            }
+        }
+        return;
+    } else if constexpr (B >= 1) {
+        constexpr int S = 2 * B;
+        constexpr int SE = NV < S * ((DC + S - 1) / S) ? NV : S * ((DC + S - 1) / S);
+        int sv[SE], si[SE];
+#pragma unroll
+        for (int q = SE - 1; q >= 0; --q) {
+            if (q == SE - 1 || (q + 1) % S == 0) {
+                sv[q] = v[q];
+                si[q] = q;
+            } else {
+                const bool take = v[q] >= sv[q + 1];
+                sv[q] = take ? v[q] : sv[q + 1];
+                si[q] = take ? q : si[q + 1];
+            }
+        }
+        int pv = 0, pi = 0;
+#pragma unroll
+        for (int t = S; t < NV; ++t) {
+            if (t % S == 0) {
+                pv = v[t];
+                pi = t;
+            } else if (v[t] > pv) {
+                pv = v[t];
+                pi = t;
+            }
+            const int j = t - 2 * B;  // the window ending at t
+            if (j >= 0 && j < DC) {
+                const bool s_wins = sv[j] >= pv;
+                m[j] = s_wins ? sv[j] : pv;
+                ia[j] = s_wins ? si[j] : pi;
+            }
+        }
+        return;
+    }
     int sv[NV], si[NV];
 #pragma unroll
     for (int q = NV - 1; q >= 0; --q) {
