@@ -110,3 +110,39 @@ def test_paired_batch_odd_and_even_band_counts(orc):
         want_s, want_x = orc.detect_polyline(img, k, bend=3)
         assert int(host(out[q][0])[0]) == want_s, q
         assert host(out[q][1]).tolist() == want_x.tolist(), q
+
+
+def test_batch_larger_than_one_pack(orc):
+    """600 images in one call.  A launch carries at most 256 images, and images
+    are grouped by band height and pixel type (FHT) and by window class (DP
+    steps): the 300 general-path images here form one group of each (64-row
+    bands, 8-bit pixels, bound 3, k = 2 or 3), so their FHT, every DP step
+    and the walks run as two packs.  The other 300 take the one-workgroup
+    path, with both pixel types, fixed bounds, the angle form and no limit.
+    Every result equals the oracle's."""
+    dev = require_gpu()
+    rng = _rng(600)
+    jobs = []
+    for q in range(600):
+        if q % 2:
+            n = int(rng.choice([2, 4, 8, 16]))
+            k = int(rng.integers(1, 6))
+            w = int(rng.integers(1, 40))
+            dt = np.uint8 if q % 3 else np.uint16
+            kind = (dict(bend=int(rng.integers(0, 12))), dict(gamma=0.4), dict(bend=10 ** 6))[q % 3]
+        else:
+            n, k, w, dt = 64, int(rng.integers(2, 4)), int(rng.integers(20, 90)), np.uint8
+            kind = dict(bend=3)
+        top = 255 if dt == np.uint8 else 65535
+        img = rng.integers(0, top + 1, size=(n * k, w)).astype(dt)
+        jobs.append((img, k, kind.get("bend"), kind.get("gamma")))
+    want = [orc.detect_polyline(img, k, bend=b, gamma=g) for img, k, b, g in jobs]
+    imgs = [to_device(img, dev) for img, _, _, _ in jobs]
+    from paper_1912_01884_amd import fhtp
+    announce("batch of 600 images")
+    out = fhtp.detect_batch(imgs, [j[1] for j in jobs], bends=[j[2] for j in jobs],
+                            gammas=[j[3] for j in jobs])
+    torch.cuda.synchronize()
+    for q, (s, x) in enumerate(want):
+        assert int(host(out[q][0])[0]) == s, q
+        assert host(out[q][1]).tolist() == x.tolist(), q
