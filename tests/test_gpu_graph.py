@@ -5,6 +5,11 @@ different image and a host synchronisation), and every replay's outputs are
 compared with the eager call's.
 """
 
+import json
+import os
+import subprocess
+import sys
+
 import numpy as np
 import pytest
 import torch
@@ -200,3 +205,36 @@ def test_plan_with_scanned_windows(orc):
             assert int(host(a)[0]) == w_s, rep
             assert host(b).tolist() == w_x.tolist(), rep
     plan.destroy()
+
+
+_FIRST_CALL = """
+import json, sys
+import torch
+import synth
+from paper_1912_01884_amd import fhtp
+s = synth.make_config(sys.argv[1])
+img = torch.from_numpy(s.image).to("cuda:0")
+plan = fhtp.Plan([img], [s.k], bends=[s.bend])
+plan.launch()
+torch.cuda.synchronize()
+(sc, xs), = plan.results
+print(json.dumps([int(sc.cpu()[0]), xs.cpu().tolist()]))
+"""
+
+
+@pytest.mark.parametrize("cfg", ["64x64", "1024x1024"])
+def test_plan_as_first_call_in_a_fresh_process(orc, cfg):
+    """A plan recorded by a process that has made no other library call.  Its
+    first-use set-up then runs while the capture is open: raising the
+    one-workgroup kernel's LDS limit and the FHT's occupancy query, neither of
+    them stream work (the plan's second stream is made before the capture)."""
+    require_gpu()
+    s = synth.make_config(cfg)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    announce(f"plan as a fresh process's first call: {cfg}")
+    r = subprocess.run([sys.executable, "-c", _FIRST_CALL, cfg], cwd=root, capture_output=True,
+                       text=True, timeout=180, env=dict(os.environ, PYTHONPATH=root))
+    assert r.returncode == 0, r.stdout + r.stderr
+    got_s, got_x = json.loads(r.stdout.strip().splitlines()[-1])
+    want_s, want_x = orc.detect_polyline(s.image, s.k, bend=s.bend)
+    assert got_s == want_s and got_x == want_x.tolist()
