@@ -113,9 +113,10 @@ struct WalkJob {
     int n, w, k;
     int bound, full;
     // Bands pair_lo .. pair_top were made two per launch (pair_top 0: none).
-    // For i = pair_lo, pair_lo + 2, ... < pair_top, plane i holds, at the cell
-    // (d_i, x_{i+1}) of plane i-1, the link d_{i+2} that follows d_{i+1}: both
-    // links of a pair are read at one index.
+    // For i = pair_lo, pair_lo + 2, ... < pair_top, planes i-1 and i together
+    // hold one plane of PairLinks<AT> (same row pitch): at the cell
+    // (d_i, x_{i+1}), d_{i+1} in the low half and the link d_{i+2} that
+    // follows it in the high half, so one load gives both links of a pair.
     int pair_lo, pair_top;
     // Bands 1 .. tri_top were made three per launch (0: none): for i = 1, 4,
     // 7, ..., planes i-1, i and i+1 hold d_{i+1}, d_{i+2} and d_{i+3} at the
@@ -326,6 +327,13 @@ __device__ __forceinline__ RowView row_view(const void* plane, int pitch, int es
         (short)0, cnt * pitch * esz, 0x00020000);
     return v;
 }
+
+// The two links of a pair of steps in one element: the low half holds a
+// cell's own choice, the high half the link after it.
+template <typename AT>
+using PairLinks = std::conditional_t<sizeof(AT) == 1, uint16_t, uint32_t>;
+template <typename AT>
+constexpr int kLinkBits = 8 * (int)sizeof(AT);
 
 // Byte offset of a row inside the view (0 for rows it does not cover, whose
 // lanes are masked by an out-of-range lane offset instead).
@@ -689,8 +697,10 @@ struct DpPairJob {
     const void* h1;      // H_{i+1} (int32, or uint16 for narrow tables: the kernel's TT)
     const void* h0;      // H_i
     int32_t* vout;       // V_i
-    void* a1;            // A_{i+2} plane: at each cell of step i, the link after next
-    void* a0;            // A_{i+1} plane
+    // At each cell of step i, PairLinks<AT>: its own choice (row of A_{i+1})
+    // and the link after next (the choice of the chosen cell of step i+1);
+    // the plane spans what two planes of AT would
+    void* a;
     int vin_pitch, h_pitch, v_pitch, a_pitch;
     int n, w, items_x, items_y;
     int item0;  // first workgroup of this image in the launch
@@ -725,7 +735,6 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     constexpr int SC = 64 + kStrip - 1;    // successor columns of one strip
     constexpr int NV1 = kStrip + 2 * B;
     constexpr int NV2 = kPairDC + 2 * B;
-    constexpr int esz = (int)sizeof(AT);
     constexpr int LP = kStrip - 1;         // padding on either side of an LDS row
     constexpr int LWP = 64 + 2 * LP;       // strip cells outside the tile land in the padding
     __shared__ int mid[NS * kStrip][LWP];  // V_{i+1}(X0 + c, row m0 + q) at [q][LP + c]
@@ -785,7 +794,6 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     const RowView vv = row_view(a.vin, a.vin_pitch, 4, m0 - B, NS * kStrip + 2 * B, D);
     const RowView h1v = row_view(a.h1, a.h_pitch, (int)hsz, m0, RM, D);
     const unsigned int vp = (unsigned int)a.vin_pitch * 4u;
-    const unsigned int ap = (unsigned int)a.a_pitch * (unsigned int)esz;
     for (int t = threadIdx.x; t < NS * SC; t += 64 * kPairWaves) {
         const int s = t / SC, c = t - s * SC;
         const int q0 = s * kStrip;             // mid row of the strip's first displacement
@@ -858,15 +866,16 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
     for (int q = 0; q < NV2; ++q) v2[q] = lcol[q * LWP];
     int m2[kPairDC], ia2[kPairDC];
     window_max<B, kPairDC>(v2, m2, ia2);
-    const RowView aview = row_view(a.a0, a.a_pitch, esz, r2, kPairDC, D);
-    const RowView a2view = row_view(a.a1, a.a_pitch, esz, r2, kPairDC, D);  // links after next
+    constexpr int psz = (int)sizeof(PairLinks<AT>);
+    const RowView aview = row_view(a.a, a.a_pitch, psz, r2, kPairDC, D);
     const RowView oview = row_view(a.vout, a.v_pitch, 4, r2, kPairDC, D);
     const unsigned int op = (unsigned int)a.v_pitch * 4u;
     // cell j: row r2 + j < D; V_i(x, d) at x = xp - d2 - j in [0, w)
     const int jn = col_ok ? min(kPairDC, D - r2) : 0;
     const int xj = xp - d2;  // x of cell j is xj - j
     const unsigned int ob = (unsigned int)xj * 4u;
-    const unsigned int ab2 = (unsigned int)xp * (unsigned int)esz;
+    const unsigned int ab2 = (unsigned int)xp * (unsigned int)psz;
+    const unsigned int pp = (unsigned int)a.a_pitch * (unsigned int)psz;
 #pragma unroll
     for (int j = 0; j < kPairDC; ++j) {
         const bool cell = j < jn;
@@ -876,14 +885,12 @@ __global__ __launch_bounds__(64 * kPairWaves) void dp_pair_fixed(DpPairPack<CAP>
         const int ra = r2 - B + ia2[j];
         const unsigned int av = (unsigned int)(ra < 0 ? 0 : ra);
         const unsigned int av2 = nxt[wave * kPairDC + ia2[j]][LP + lane];  // the chosen cell's choice
-        const unsigned int aoff = cell ? ab2 + j * ap : kOut;
-        if constexpr (sizeof(AT) == 1) {
-            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av, aview.rs, (int)aoff, 0, kStoreScope);
-            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)av2, a2view.rs, (int)aoff, 0, kStoreScope);
-        } else {
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av, aview.rs, (int)aoff, 0, kStoreScope);
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)av2, a2view.rs, (int)aoff, 0, kStoreScope);
-        }
+        const unsigned int aoff = cell ? ab2 + j * pp : kOut;
+        const unsigned int both = av | (av2 << kLinkBits<AT>);
+        if constexpr (sizeof(AT) == 1)
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)both, aview.rs, (int)aoff, 0, kStoreScope);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(both, aview.rs, (int)aoff, 0, kStoreScope);
         __builtin_amdgcn_raw_buffer_store_b32(val, oview.rs, (int)(live ? ob + j * (op - 4u) : kOut),
                                               0, kStoreScope);
     }
@@ -1601,12 +1608,12 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
 }
 
 // Four bands in one round trip over two pairs of steps made in one launch
-// each (odd i, i + 3 <= pair_top), windows of at most 31 displacements.  The
-// planes of a pair give both of its links at the index of its lower band's
+// each (odd i, i + 3 <= pair_top), windows of at most 31 displacements.  A
+// pair's plane gives both of its links at the index of its lower band's
 // cell, so with x_i and d_i known one load gives d_{i+1} and d_{i+2}, and the
-// next pair's two links are loaded for every candidate (d_{i+1}, d_{i+2}) as in
+// next pair's links are loaded for every candidate (d_{i+1}, d_{i+2}) as in
 // walk_three (lanes 0-31 take the even d_{i+1} of the window, lanes 32-63 the
-// odd ones, U candidates per lane, two planes each).
+// odd ones, U candidates per lane, one load each).
 template <typename AT, int U>
 __device__ __forceinline__ bool walk_four(const WalkJob& a, int lane, int& x, int& r, int& i) {
     const int n = a.n, w = a.w, D = 2 * n - 1;
@@ -1614,27 +1621,27 @@ __device__ __forceinline__ bool walk_four(const WalkJob& a, int lane, int& x, in
     const unsigned int pitch = (unsigned int)a.a_pitch;
     const int xn = x + r - (n - 1);
     if (xn < 0 || xn >= w || r < 0 || r >= D) return false;
-    const AT* Q1 = static_cast<const AT*>(a.a_base) + (size_t)(i - 1) * a.a_plane;  // d_{i+1}
-    const AT* Q2 = Q1 + a.a_plane;                                                  // d_{i+2}
-    const AT* Q3 = Q2 + a.a_plane;                                                  // d_{i+3}
-    const AT* Q4 = Q3 + a.a_plane;                                                  // d_{i+4}
+    using PT = PairLinks<AT>;
+    constexpr unsigned int lo_mask = (1u << kLinkBits<AT>) - 1u;
+    const AT* A = static_cast<const AT*>(a.a_base);
+    const PT* Q12 = reinterpret_cast<const PT*>(A + (size_t)(i - 1) * a.a_plane);  // d_{i+1}, d_{i+2}
+    const PT* Q34 = reinterpret_cast<const PT*>(A + (size_t)(i + 1) * a.a_plane);  // d_{i+3}, d_{i+4}
     const unsigned int off = (unsigned int)r * pitch + (unsigned int)xn;
-    const int rn_v = Q1[off], rm_v = Q2[off];
+    const unsigned int p12 = Q12[off];
     const int l2 = lane & 31;
-    int s3[U], s4[U];
+    unsigned int s34[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int c1 = r - B + 2 * u + (lane >> 5);
         const int c2 = min(max(c1 - B + l2, 0), D - 1);
         const int x3 = min(max(xn + c1 + c2 - 2 * (n - 1), 0), w - 1);
-        const unsigned int o3 = (unsigned int)c2 * pitch + (unsigned int)x3;
-        s3[u] = Q3[o3];
-        s4[u] = Q4[o3];
+        s34[u] = Q34[(unsigned int)c2 * pitch + (unsigned int)x3];
     }
     // As in walk_three: no branch until the loads have been used, and the
     // pointers every lane loaded alike are taken as wave-uniform values.
-    const int rn = __builtin_amdgcn_readfirstlane(rn_v);
-    const int r2 = __builtin_amdgcn_readfirstlane(rm_v);
+    const unsigned int p12u = __builtin_amdgcn_readfirstlane(p12);
+    const int rn = (int)(p12u & lo_mask);
+    const int r2 = (int)(p12u >> kLinkBits<AT>);
     const int l1 = rn - (r - B);
     const bool ok1 = (unsigned)l1 < (unsigned)L1 && rn < D;
     const int xnn = xn + rn - (n - 1);
@@ -1643,15 +1650,13 @@ __device__ __forceinline__ bool walk_four(const WalkJob& a, int lane, int& x, in
     const int x3 = xnn + r2 - (n - 1);
     const bool ok3 = ok2 && x3 >= 0 && x3 < w;
     const int slot = l1 >> 1;
-    int m3 = s3[0], m4 = s4[0];
+    unsigned int m34 = s34[0];
 #pragma unroll
-    for (int u = 1; u < U; ++u) {
-        m3 = slot == u ? s3[u] : m3;
-        m4 = slot == u ? s4[u] : m4;
-    }
+    for (int u = 1; u < U; ++u) m34 = slot == u ? s34[u] : m34;
     const int src = ((l1 & 1) << 5) | (l2s & 31);
-    const int r3 = __builtin_amdgcn_readlane(m3, src);
-    const int r4 = __builtin_amdgcn_readlane(m4, src);
+    const unsigned int p34 = __builtin_amdgcn_readlane(m34, src);
+    const int r3 = (int)(p34 & lo_mask);
+    const int r4 = (int)(p34 >> kLinkBits<AT>);
     const int l3 = r3 - (r2 - B);
     const int x4 = x3 + r3 - (n - 1);
     const bool ok4 = ok3 && (unsigned)l3 < (unsigned)L1 && r3 >= 0 && r3 < D && x4 >= 0 && x4 < w;
@@ -1777,10 +1782,12 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
                     if (lane == 0) *a.score = -1;
                     return;
                 }
-                const AT* Pi = A + (size_t)(i - 1) * a.a_plane;
-                const unsigned int off = (unsigned int)r * pitch + (unsigned int)xn;
-                const int rn = __builtin_amdgcn_readfirstlane((int)Pi[off]);
-                const int r2 = __builtin_amdgcn_readfirstlane((int)Pi[a.a_plane + off]);
+                const PairLinks<AT>* Pi =
+                    reinterpret_cast<const PairLinks<AT>*>(A + (size_t)(i - 1) * a.a_plane);
+                const unsigned int both = __builtin_amdgcn_readfirstlane(
+                    (unsigned int)Pi[(unsigned int)r * pitch + (unsigned int)xn]);
+                const int rn = (int)(both & ((1u << kLinkBits<AT>) - 1u));
+                const int r2 = (int)(both >> kLinkBits<AT>);
                 const int xnn = xn + rn - (n - 1);
                 if (rn >= D || xnn < 0 || xnn >= w) {
                     if (lane == 0) *a.score = -1;
@@ -2500,8 +2507,7 @@ hipError_t run_steps_grouped(const DpClass& c, int G, const std::vector<const Dp
         a.h1 = band_table(J, i);
         a.h0 = band_table(J, i - 1);
         a.vout = plane_of(J, j);
-        a.a1 = A + (size_t)(i - 1) * plane;  // A_{i+1}
-        a.a0 = A + (size_t)(i - 2) * plane;  // A_i
+        a.a = A + (size_t)(i - 2) * plane;  // planes i-2 and i-1: A_i with the links after
         a.h_pitch = g.W;
         a.v_pitch = g.pitch;
         a.a_pitch = g.pitch;
