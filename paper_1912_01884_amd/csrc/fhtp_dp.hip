@@ -1607,69 +1607,99 @@ __device__ __forceinline__ bool walk_three(const WalkJob& a, int lane, int& x, i
     return true;
 }
 
-// Four bands in one round trip over two pairs of steps made in one launch
-// each (odd i, i + 3 <= pair_top), windows of at most 31 displacements.  A
-// pair's plane gives both of its links at the index of its lower band's
-// cell, so with x_i and d_i known one load gives d_{i+1} and d_{i+2}, and the
-// next pair's links are loaded for every candidate (d_{i+1}, d_{i+2}) as in
-// walk_three (lanes 0-31 take the even d_{i+1} of the window, lanes 32-63 the
-// odd ones, U candidates per lane, one load each).
+// Four bands per round trip over the pairs of steps made in one launch each
+// (from i = 1 while i + 3 <= pair_top), windows of at most 31 displacements.
+// A pair's plane gives both of its links at the index of its lower band's
+// cell, so with x_i and d_i known one load gives d_{i+1} and d_{i+2}; in the
+// same round trip the next pair's links are loaded for every candidate
+// (d_{i+1}, d_{i+2}) = (d_i - B + q1, d_i - 2B + q1 + q2), q1, q2 in [0, L1):
+// candidate t = q1 * L1 + q2 is slot t / 64 of lane t % 64, so U slots cover
+// the L1 * L1 candidates.  Loads are buffer loads through views of the rows a
+// round trip can reach (row d_i of one pair, rows d_i - 2B .. d_i + 2B of the
+// next): a candidate whose index leaves its view reads 0 instead of faulting,
+// and the one finally selected always lies inside.  Returns false when a link
+// leaves the image (the caller reports no polyline).
 template <typename AT, int U>
-__device__ __forceinline__ bool walk_four(const WalkJob& a, int lane, int& x, int& r, int& i) {
+__device__ __forceinline__ bool walk_fours(const WalkJob& a, int lane, int& x, int& r, int& i) {
+    using PT = PairLinks<AT>;
+    constexpr unsigned int lo_mask = (1u << kLinkBits<AT>) - 1u;
+    constexpr unsigned int psz = sizeof(PT);
     const int n = a.n, w = a.w, D = 2 * n - 1;
     const int B = a.bound, L1 = 2 * B + 1;
     const unsigned int pitch = (unsigned int)a.a_pitch;
-    const int xn = x + r - (n - 1);
-    if (xn < 0 || xn >= w || r < 0 || r >= D) return false;
-    using PT = PairLinks<AT>;
-    constexpr unsigned int lo_mask = (1u << kLinkBits<AT>) - 1u;
-    const AT* A = static_cast<const AT*>(a.a_base);
-    const PT* Q12 = reinterpret_cast<const PT*>(A + (size_t)(i - 1) * a.a_plane);  // d_{i+1}, d_{i+2}
-    const PT* Q34 = reinterpret_cast<const PT*>(A + (size_t)(i + 1) * a.a_plane);  // d_{i+3}, d_{i+4}
-    const unsigned int off = (unsigned int)r * pitch + (unsigned int)xn;
-    const unsigned int p12 = Q12[off];
-    const int l2 = lane & 31;
-    unsigned int s34[U];
+    // this lane's candidates: q1 (the window position of d_{i+1}) and the row
+    // offset q1 + q2 - 2B of d_{i+2} from d_i, fixed for the whole walk
+    int q1[U], dq[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int c1 = r - B + 2 * u + (lane >> 5);
-        const int c2 = min(max(c1 - B + l2, 0), D - 1);
-        const int x3 = min(max(xn + c1 + c2 - 2 * (n - 1), 0), w - 1);
-        s34[u] = Q34[(unsigned int)c2 * pitch + (unsigned int)x3];
+        const int t = u * 64 + lane;
+        q1[u] = t / L1;
+        dq[u] = t - q1[u] * (L1 - 1) - 2 * B;  // q1 + q2 - 2B with q2 = t - q1 * L1
     }
-    // As in walk_three: no branch until the loads have been used, and the
-    // pointers every lane loaded alike are taken as wave-uniform values.
-    const unsigned int p12u = __builtin_amdgcn_readfirstlane(p12);
-    const int rn = (int)(p12u & lo_mask);
-    const int r2 = (int)(p12u >> kLinkBits<AT>);
-    const int l1 = rn - (r - B);
-    const bool ok1 = (unsigned)l1 < (unsigned)L1 && rn < D;
-    const int xnn = xn + rn - (n - 1);
-    const int l2s = r2 - (rn - B);
-    const bool ok2 = ok1 && xnn >= 0 && xnn < w && (unsigned)l2s < (unsigned)L1 && r2 >= 0 && r2 < D;
-    const int x3 = xnn + r2 - (n - 1);
-    const bool ok3 = ok2 && x3 >= 0 && x3 < w;
-    const int slot = l1 >> 1;
-    unsigned int m34 = s34[0];
+    const AT* A = static_cast<const AT*>(a.a_base);
+    while (i + 3 <= a.pair_top) {
+        const int xn = x + r - (n - 1);
+        if (xn < 0 || xn >= w || r < 0 || r >= D) return false;
+        const RowView v12 = row_view(A + (size_t)(i - 1) * a.a_plane, a.a_pitch, psz, r, 1, D);
+        const RowView v34 = row_view(A + (size_t)(i + 1) * a.a_plane, a.a_pitch, psz, r - 2 * B,
+                                     4 * B + 1, D);
+        const unsigned int off = (unsigned int)xn * psz;
+        unsigned int p12;
+        if constexpr (psz == 2)
+            p12 = __builtin_amdgcn_raw_buffer_load_b16(v12.rs, (int)off, 0, 0);
+        else
+            p12 = __builtin_amdgcn_raw_buffer_load_b32(v12.rs, (int)off, 0, 0);
+        // candidate cell of the next pair: row c2 = r + dq, column
+        // x_{i+3} = xn + d_{i+1} + d_{i+2} with d_{i+1} = r - B + q1 - (n - 1)
+        // (offsets relative to the view's first row; a row before it wraps to
+        // a huge offset, one past its end lies beyond its records)
+        const int base_x = xn + 2 * r - B - 2 * (n - 1);
+        const int rel = r - v34.base;
+        unsigned int s34[U];
 #pragma unroll
-    for (int u = 1; u < U; ++u) m34 = slot == u ? s34[u] : m34;
-    const int src = ((l1 & 1) << 5) | (l2s & 31);
-    const unsigned int p34 = __builtin_amdgcn_readlane(m34, src);
-    const int r3 = (int)(p34 & lo_mask);
-    const int r4 = (int)(p34 >> kLinkBits<AT>);
-    const int l3 = r3 - (r2 - B);
-    const int x4 = x3 + r3 - (n - 1);
-    const bool ok4 = ok3 && (unsigned)l3 < (unsigned)L1 && r3 >= 0 && r3 < D && x4 >= 0 && x4 < w;
-    if (lane == 0) {
-        if (ok1) a.xs[i + 1] = xn;
-        if (ok2) a.xs[i + 2] = xnn;
-        if (ok3) a.xs[i + 3] = x3;
-        if (ok4) a.xs[i + 4] = x4;
+        for (int u = 0; u < U; ++u) {
+            const int c2 = rel + dq[u];
+            const int x3 = base_x + q1[u] + dq[u];
+            const unsigned int o3 = ((unsigned int)c2 * pitch + (unsigned int)x3) * psz;
+            if constexpr (psz == 2)
+                s34[u] = __builtin_amdgcn_raw_buffer_load_b16(v34.rs, (int)o3, 0, 0);
+            else
+                s34[u] = __builtin_amdgcn_raw_buffer_load_b32(v34.rs, (int)o3, 0, 0);
+        }
+        // No branch until the loads have been used; the pair every lane
+        // loaded alike is taken as a wave-uniform value.
+        const unsigned int p12u = __builtin_amdgcn_readfirstlane(p12);
+        const int rn = (int)(p12u & lo_mask);
+        const int r2 = (int)(p12u >> kLinkBits<AT>);
+        const int l1 = rn - (r - B);
+        const bool ok1 = (unsigned)l1 < (unsigned)L1 && rn < D;
+        const int xnn = xn + rn - (n - 1);
+        const int l2s = r2 - (rn - B);
+        const bool ok2 = ok1 && xnn >= 0 && xnn < w && (unsigned)l2s < (unsigned)L1 && r2 >= 0 && r2 < D;
+        const int x3 = xnn + r2 - (n - 1);
+        const bool ok3 = ok2 && x3 >= 0 && x3 < w;
+        const int tsel = l1 * L1 + l2s;  // the candidate that was taken
+        const int slot = tsel >> 6;
+        unsigned int m34 = s34[0];
+#pragma unroll
+        for (int u = 1; u < U; ++u) m34 = slot == u ? s34[u] : m34;
+        const unsigned int p34 = __builtin_amdgcn_readlane(m34, tsel & 63);
+        const int r3 = (int)(p34 & lo_mask);
+        const int r4 = (int)(p34 >> kLinkBits<AT>);
+        const int l3 = r3 - (r2 - B);
+        const int x4 = x3 + r3 - (n - 1);
+        const bool ok4 = ok3 && (unsigned)l3 < (unsigned)L1 && r3 >= 0 && r3 < D && x4 >= 0 && x4 < w;
+        if (lane == 0) {
+            if (ok1) a.xs[i + 1] = xn;
+            if (ok2) a.xs[i + 2] = xnn;
+            if (ok3) a.xs[i + 3] = x3;
+            if (ok4) a.xs[i + 4] = x4;
+        }
+        if (!ok4) return false;
+        x = x4;
+        r = r4;
+        i += 4;
     }
-    if (!ok4) return false;
-    x = x4;
-    r = r4;
-    i += 4;
     return true;
 }
 
@@ -1766,11 +1796,14 @@ __global__ __launch_bounds__(64) void walk(WalkPack<CAP> pk) {
             if (i >= a.pair_lo && !((i - a.pair_lo) & 1) && i < a.pair_top) {
                 // a pair of links made in one launch (see WalkJob::pair_top)
                 if (narrow && a.pair_lo == 1 && i + 3 <= a.pair_top) {
-                    const bool ok = L1 <= 7    ? walk_four<AT, 4>(a, lane, x, r, i)
-                                    : L1 <= 11 ? walk_four<AT, 6>(a, lane, x, r, i)
-                                    : L1 <= 17 ? walk_four<AT, 9>(a, lane, x, r, i)
-                                    : L1 <= 23 ? walk_four<AT, 12>(a, lane, x, r, i)
-                                               : walk_four<AT, 16>(a, lane, x, r, i);
+                    // U slots of 64 candidates cover L1 * L1.  Past 16 slots
+                    // (L1 = 33) the gathers of one round trip cost more than
+                    // the round trips saved, and two bands per trip are faster.
+                    const bool ok = L1 <= 7    ? walk_fours<AT, 1>(a, lane, x, r, i)
+                                    : L1 <= 11 ? walk_fours<AT, 2>(a, lane, x, r, i)
+                                    : L1 <= 17 ? walk_fours<AT, 5>(a, lane, x, r, i)
+                                    : L1 <= 23 ? walk_fours<AT, 9>(a, lane, x, r, i)
+                                               : walk_fours<AT, 16>(a, lane, x, r, i);
                     if (!ok) {
                         if (lane == 0) *a.score = -1;
                         return;
