@@ -34,16 +34,16 @@ HBM_PEAK_GBPS = 8000.0
 TRAFFIC = {
     "fht_reg_kernel": {"source": "paper_1912_01884_amd/csrc/fhtp_fht.hip",
                       "source_sha256": "e7eee6e6575463104e02e08783cd3137e37f8275f260b872fb3e9b5f019fc535",
-                      "fetch_bytes": 36875468, "write_bytes": 142952416},
+                      "fetch_bytes": 36827289, "write_bytes": 142582784},
     "dp_pair_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
-                     "source_sha256": "10df57a41b3a5b2fb5df0e1028caadb6c4cb9def387f750a52ceb4cdda294877",
-                     "fetch_bytes": 13977651, "write_bytes": 6653440},
+                     "source_sha256": "a6bf6ca8288b017f2832837c1fe9d972cf6ff7e6104683c978afdf24e9237859",
+                     "fetch_bytes": 13988813, "write_bytes": 6653440},
     "dp_step_fixed": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
-                     "source_sha256": "10df57a41b3a5b2fb5df0e1028caadb6c4cb9def387f750a52ceb4cdda294877",
-                     "fetch_bytes": 8690742, "write_bytes": 6144},
+                     "source_sha256": "a6bf6ca8288b017f2832837c1fe9d972cf6ff7e6104683c978afdf24e9237859",
+                     "fetch_bytes": 8680520, "write_bytes": 6144},
     "walk": {"source": "paper_1912_01884_amd/csrc/fhtp_dp.hip",
-            "source_sha256": "10df57a41b3a5b2fb5df0e1028caadb6c4cb9def387f750a52ceb4cdda294877",
-            "fetch_bytes": 139758, "write_bytes": 192},
+            "source_sha256": "a6bf6ca8288b017f2832837c1fe9d972cf6ff7e6104683c978afdf24e9237859",
+            "fetch_bytes": 67448, "write_bytes": 192},
 }
 
 
