@@ -172,13 +172,47 @@ PAIRED = [
 ]
 
 
-@pytest.mark.parametrize("B", [0, 1, 3, 7, 8, 9, 12, 16])
+@pytest.mark.parametrize("B", [0, 1, 3, 4, 7, 8, 9, 12, 15, 16])
 @pytest.mark.parametrize("h,w,k", PAIRED, ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in PAIRED])
 def test_detect_paired_steps(dev, F, orc, h, w, k, B):
     img = _img(h, w, np.uint8, 31 * h + w + B, 3 if B % 2 == 0 else None)
     want_s, want_x = orc.detect_polyline(img, k, bend=B)
     announce(f"detect paired {h}x{w} k={k} B={B}")
     with general_path():  # the two-step kernel, also where the image is small
+        sc, xs = F.detect_polyline(to_device(img, dev), k, bend=B)
+    assert int(host(sc)[0]) == want_s
+    assert host(xs).tolist() == want_x.tolist()
+
+
+EXTREME = [
+    # (n, k, w, bend): every link of the planted polyline at a displacement of
+    # -(n-1) or n-1, the first or last row of the back-pointer planes, so the
+    # walk's candidate rows run past the planes' edges
+    (16, 10, 203, 3),
+    (16, 10, 203, 8),
+    (16, 10, 203, 15),
+    (256, 6, 1600, 8),   # 16-bit back-pointers
+]
+
+
+@pytest.mark.parametrize("sign", [-1, 1])
+@pytest.mark.parametrize("n,k,w,B", EXTREME, ids=[f"n{c[0]}k{c[1]}w{c[2]}b{c[3]}" for c in EXTREME])
+def test_walk_along_extreme_displacements(dev, F, orc, n, k, w, B, sign):
+    """A bright polyline whose links all shift by sign*(n-1) (one pixel per
+    row inside a band, each band starting where the last one ended) on faint
+    noise: the best polyline follows it, every link at the edge of the
+    displacement range."""
+    img = _img(n * k, w, np.uint8, 7 * n + k + B + (sign > 0), 20)
+    x = 10 if sign > 0 else w - 11
+    for i in range(k):
+        for j in range(n):
+            img[i * n + j, x + sign * j] = 255
+        x += sign * (n - 1)
+    want_s, want_x = orc.detect_polyline(img, k, bend=B)
+    links = np.diff(want_x)
+    assert (links == sign * (n - 1)).all(), links  # the oracle takes the planted polyline
+    announce(f"extreme links n={n} k={k} w={w} B={B} sign={sign}")
+    with general_path():  # pairs and the general walk, also where the image is small
         sc, xs = F.detect_polyline(to_device(img, dev), k, bend=B)
     assert int(host(sc)[0]) == want_s
     assert host(xs).tolist() == want_x.tolist()
